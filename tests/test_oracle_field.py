@@ -1,0 +1,75 @@
+"""Pins for the oracle's external galactic field (Eq. 3 term F_ext; bulge + disk + halo):
+finite differences of its potential, circular-speed closed form, Sect. 6.1's orbital period of
+about 60 time units at R = 8, and exact L_z conservation for the axisymmetric field (Table 2)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1003_3896_amd import inputs
+
+
+def test_acceleration_is_minus_gradient(oracle_mod):
+    rng = np.random.default_rng(3)
+    pts = np.concatenate([rng.uniform(-12, 12, (40, 3)), rng.uniform(-0.5, 0.5, (10, 3)),
+                          np.array([[8.0, 0.0, 0.0], [8.0, 0.0, 0.2], [0.3, 0.1, -2.0]])])
+    a, _ = oracle_mod.ext_field(pts)
+    h = 1e-5
+    fd = np.zeros_like(pts)
+    for c in range(3):
+        dp = np.zeros(3)
+        dp[c] = h
+        fd[:, c] = -(oracle_mod.ext_field(pts + dp)[1] - oracle_mod.ext_field(pts - dp)[1]) / (2 * h)
+    err = np.linalg.norm(a - fd, axis=1) / np.linalg.norm(a, axis=1)
+    assert err.max() < 1e-8
+
+
+def test_component_closed_forms(oracle_mod):
+    """Each component alone against its textbook potential at a point."""
+    x = np.array([[1.5, -0.5, 0.7]])
+    R2 = 1.5 ** 2 + 0.5 ** 2
+    r = math.sqrt(R2 + 0.49)
+    # bulge only
+    _, phi = oracle_mod.ext_field(x, galaxy=(2.0, 0.5, 0.0, 1.0, 1.0, 0.0, 1.0))
+    assert abs(phi[0] + 2.0 / (r + 0.5)) < 1e-15
+    # disk only
+    _, phi = oracle_mod.ext_field(x, galaxy=(0.0, 1.0, 3.0, 2.0, 0.3, 0.0, 1.0))
+    assert abs(phi[0] + 3.0 / math.sqrt(R2 + (2.0 + math.sqrt(0.49 + 0.09)) ** 2)) < 1e-15
+    # halo only
+    _, phi = oracle_mod.ext_field(x, galaxy=(0.0, 1.0, 0.0, 1.0, 1.0, 0.6, 5.0))
+    assert abs(phi[0] - 0.18 * math.log(r * r + 25.0)) < 1e-15
+    # G scales bulge and disk but not the halo (its amplitude is vh^2)
+    a1, _ = oracle_mod.ext_field(x, G=1.0, galaxy=(1.0, 0.5, 1.0, 1.0, 0.3, 0.0, 1.0))
+    a2, _ = oracle_mod.ext_field(x, G=2.0, galaxy=(1.0, 0.5, 1.0, 1.0, 0.3, 0.0, 1.0))
+    np.testing.assert_allclose(a2, 2 * a1, rtol=1e-15)
+
+
+def test_circular_speed_and_period(oracle_mod):
+    a, _ = oracle_mod.ext_field(np.array([[inputs.ORBIT_R, 0.0, 0.0]]))
+    vc = math.sqrt(inputs.ORBIT_R * abs(a[0, 0]))
+    assert abs(vc - inputs.V_CIRC_8) < 1e-12
+    period = 2 * math.pi * inputs.ORBIT_R / vc
+    assert 59.0 < period < 61.0
+    assert a[0, 1] == 0 and a[0, 2] == 0
+
+
+def test_test_particle_orbit_conserves_energy_and_lz(oracle_mod):
+    """A massless tracer on an inclined orbit: sym6 keeps E to ~1e-12 and L_z to rounding."""
+    pos = np.array([[8.0, 0.0, 0.3]])
+    vel = np.array([[0.05, inputs.V_CIRC_8, 0.04]])
+    m = np.array([1.0])
+    e0 = oracle_mod.energy(pos, vel, m, 1.0, 0.0, field=True)
+    acc = oracle_mod.total_accel(pos, m, 1.0, 0.0, field=True)
+    p, v, _ = oracle_mod.step(pos, vel, m, acc, 0.05, 1200, "sym6", 1.0, 0.0, field=True)
+    e1 = oracle_mod.energy(p, v, m, 1.0, 0.0, field=True)
+    assert abs(e1[3] - e0[3]) / abs(e0[3]) < 1e-11
+    assert abs(e1[9] - e0[9]) / abs(e0[9]) < 1e-13
+    # it went about once around (t = 60)
+    assert np.linalg.norm(p[0, :2]) > 6.0
+
+
+def test_torque_of_axisymmetric_field_has_no_z_component(oracle_mod):
+    pos, vel, m = inputs.plummer(256, 5)
+    pos, vel = inputs.on_orbit(pos, vel)
+    e = oracle_mod.energy(pos, vel, m, 1.0, 1e-3, field=True)
+    assert abs(e[12]) < 1e-14 * abs(e[10:12]).max() + 1e-16

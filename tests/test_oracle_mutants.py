@@ -1,0 +1,113 @@
+"""The oracle's pins are strong enough: plant a plausible mistake in a COPY of the oracle source
+(on the CPU, never in the HIP path), rebuild it, and check that at least one pin rejects it."""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1003_3896_amd import inputs
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "nbody_oracle.c")
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("dx-sign", "const double dx = pos[3 * j] - xi;", "const double dx = xi - pos[3 * j];"),
+    ("softening-dropped", "dz * dz + e2;", "dz * dz;"),
+    ("wrong-power", "const double inv3 = inv * inv * inv;", "const double inv3 = inv * inv;"),
+    ("self-term-kept", "if (j == i) continue;", "if (j == i && e2 == 0.0) continue;"),
+    ("y-uses-x", "const double dy = pos[3 * j + 1] - yi;", "const double dy = pos[3 * j] - yi;"),
+    ("kick-unmerged", "kick8[k] = 0.5 * (w[k - 1] + w[k]);", "kick8[k] = w[k];"),
+    ("coef-digit", "W2 = 0.235573213359357;", "W2 = 0.235573213359957;"),
+    ("drift-uses-acc", "pos[i] = pos[i] + c * vel[i];", "pos[i] = pos[i] + c * vel[i] * 0.999999;"),
+    ("disk-exponent", "const double D3 = D2 * D;", "const double D3 = D2 * D2;"),
+    ("disk-z-factor", "G * Md * As / (D3 * s);", "G * Md / (D3 * s);"),
+    ("halo-sign", "const double ph = 0.5 * vh * vh * log(r2 + dh * dh);",
+     "const double ph = -0.5 * vh * vh * log(r2 + dh * dh);"),
+    ("energy-half-missing", "nsum_add(&W, 0.5 * m * pot_scratch[i]);", "nsum_add(&W, m * pot_scratch[i]);"),
+    ("kinetic-half-missing", "nsum_add(&K, 0.5 * m * (v[0]", "nsum_add(&K, 1.0 * m * (v[0]"),
+    ("L-index", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[0]));", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[1]));"),
+    ("last-kick-missing", "kick(n, vel, acc, Kc[stages] * dt);", ";"),
+]
+
+
+def _pins():
+    """A compact run of the pins from the other oracle test files; returns names of failures."""
+    from test_oracle_pairs import _brute_decimal
+    from test_oracle_integrators import kepler_error, two_body
+    fails = []
+    rng = np.random.default_rng(1)
+    pos = rng.uniform(-1, 1, (5, 3))
+    mass = rng.uniform(0.1, 2, 5)
+    for eps in (0.0, 1e-3):
+        ra, rp = _brute_decimal(pos, mass, 1.0, eps)
+        a, p, absa = oracle.accel(pos, mass, 1.0, eps, want_pot=True, want_abs=True)
+        if not (np.linalg.norm(a - ra, axis=1) / np.maximum(absa, 1e-300)).max() <= 2e-15:
+            fails.append("brute-accel")
+        if not np.abs(p - rp).max() <= 2e-15 * np.abs(rp).max():
+            fails.append("brute-pot")
+    d, k = oracle.sym6_coefficients()
+    if abs((d ** 3).sum()) > 1e-13 or abs((d ** 5).sum()) > 1e-13 or abs(k.sum() - 1) > 1e-15:
+        fails.append("sym6-identities")
+    errs = [kepler_error(oracle, "sym6", n) for n in (128, 256, 512, 1024)]
+    s = np.polyfit(np.log([1 / 128, 1 / 256, 1 / 512, 1 / 1024]), np.log(np.maximum(errs, 1e-300)), 1)[0]
+    if abs(s - 6) > 0.3 or errs[-1] > 1e-10:
+        fails.append("sym6-order")
+    errs = [kepler_error(oracle, "leapfrog", n) for n in (256, 512, 1024, 2048)]
+    s = np.polyfit(np.log([1 / 256, 1 / 512, 1 / 1024, 1 / 2048]), np.log(np.maximum(errs, 1e-300)), 1)[0]
+    if abs(s - 2) > 0.1:
+        fails.append("leapfrog-order")
+    # field: finite differences, closed-form circular speed
+    pts = rng.uniform(-10, 10, (12, 3))
+    a, _ = oracle.ext_field(pts)
+    h = 1e-5
+    fd = np.zeros_like(pts)
+    for c in range(3):
+        dp = np.zeros(3)
+        dp[c] = h
+        fd[:, c] = -(oracle.ext_field(pts + dp)[1] - oracle.ext_field(pts - dp)[1]) / (2 * h)
+    if (np.linalg.norm(a - fd, axis=1) / np.linalg.norm(a, axis=1)).max() > 1e-8:
+        fails.append("field-fd")
+    a8, _ = oracle.ext_field(np.array([[8.0, 0, 0]]))
+    if abs(math.sqrt(8 * abs(a8[0, 0])) - inputs.V_CIRC_8) > 1e-12:
+        fails.append("field-vc")
+    # energy closed form for two bodies, with and without softening
+    p2, v2, m2 = two_body()
+    for eps in (0.0, 0.1):
+        e = oracle.energy(p2, v2, m2, 1.0, eps)
+        r = np.linalg.norm(p2[1] - p2[0])
+        K = 0.5 * (m2 * (v2 ** 2).sum(1)).sum()
+        W = -m2[0] * m2[1] / math.sqrt(r * r + eps * eps)
+        L = (m2[:, None] * np.cross(p2, v2)).sum(0)
+        if abs(e[0] - K) > 1e-15 or abs(e[1] - W) > 1e-15 or np.abs(e[7:10] - L).max() > 1e-15:
+            fails.append("energy-closed-form")
+    # angular momentum and momentum are conserved by the integrators for central pair forces
+    p3, v3, m3 = inputs.plummer(16, 3)
+    v3 = v3 + np.array([0.1, -0.2, 0.05])
+    e0 = oracle.energy(p3, v3, m3, 1.0, 0.05)
+    acc = oracle.total_accel(p3, m3, 1.0, 0.05)
+    p4, v4, _ = oracle.step(p3, v3, m3, acc, 1.0 / 128, 20, "sym6", 1.0, 0.05)
+    e1 = oracle.energy(p4, v4, m3, 1.0, 0.05)
+    if np.abs(e1[7:10] - e0[7:10]).max() > 1e-13 * np.abs(e0[7:10]).max():
+        fails.append("L-conservation")
+    return fails
+
+
+def test_unmutated_oracle_passes_all_pins(oracle_mod):
+    assert _pins() == []
+
+
+@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, oracle_mod, name, orig, bad):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, "mutation anchor not unique: " + orig
+    path = tmp_path / ("mutant_%s.c" % name)
+    path.write_text(src.replace(orig, bad))
+    lib = tmp_path / ("mutant_%s.so" % name)
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o",
+                           str(lib), str(path), "-lm"])
+    with oracle.use_library(str(lib)):
+        fails = _pins()
+    assert fails, "planted mistake %s was not caught by any pin" % name
