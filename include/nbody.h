@@ -1,0 +1,178 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) direct-summation N-body library (libnbody.so).
+ *
+ * The operations are those of NBSymple (Capuzzo-Dolcetta, Mastrobuono-Battisti & Maschietti,
+ * New Astronomy):
+ *   - the softened pairwise gravitational acceleration of Sect. 2, Eq. 5, and the softened pair
+ *     potential of Eq. 4 summed over j != i;
+ *   - the external field term of Eq. 3 (an analytic bulge + disk + halo galaxy, Sect. 3);
+ *   - the kick and drift stages of the 2nd-order leapfrog and of the 6th-order symplectic
+ *     composition of Sect. 3.1;
+ *   - the energy, momentum, angular momentum and torque diagnostics of Sect. 5.1, Eqs. 8-10.
+ *
+ * Data model
+ *   A "system" is a ragged batch of B >= 1 independent clusters (they never interact).  Cluster b
+ *   owns particles [offsets[b], offsets[b+1]) of every particle array.  All particle arrays are
+ *   DEVICE pointers to contiguous row-major float64 data: pos, vel, acc are (Ntot, 3), mass and
+ *   pot are (Ntot).  The caller owns them, the workspace and the context; the library never
+ *   allocates device memory on a call path and never synchronises the stream.
+ *
+ * Units and signs
+ *   a_i = G sum_{j != i} m_j d_ij / (|d_ij|^2 + eps_b^2)^{3/2} + a_ext(x_i),  d_ij = x_j - x_i
+ *   pot_i = -G sum_{j != i} m_j / sqrt(|d_ij|^2 + eps_b^2)   (negative for bound systems)
+ *   When eps_b > 0 the j = i term is exactly zero and the kernels may include it; when
+ *   eps_b = 0 it is excluded explicitly.  The pair sum is evaluated in full (N^2 terms per
+ *   cluster, no use of Newton's third law), as the paper does in Sect. 4.2.
+ *
+ * Precision modes (nbody_system.prec)
+ *   NB_FP32    pure single precision: pairs, accumulation and state updates in FP32; every state
+ *              value the library writes is an FP32 value stored in the float64 arrays.
+ *   NB_FP32C   FP32 pair arithmetic on coordinates taken relative to each cluster's centre of
+ *              mass (computed in FP64); per-tile FP32 partial sums folded into FP64; FP64 state.
+ *   NB_FP32DS  as NB_FP32C, but every coordinate is held as a double-single pair (hi + lo FP32)
+ *              and the coordinate difference of each pair is formed from both parts, the
+ *              precision-recovery scheme of Sect. 5.2.
+ *   NB_FP64    all FP64.
+ *
+ * Errors
+ *   Every function returns NB_OK (0) or a negative status.  All argument checks run on the host
+ *   before any HIP call, so a rejected call launches nothing and leaves every buffer untouched.
+ *   HIP runtime failures return NB_ERR_HIP.  nbody_last_error() returns a thread-local message
+ *   for the last failing call on the calling thread.
+ *
+ * Threading
+ *   A context may be used from one host thread at a time.  Calls that share a workspace must be
+ *   ordered on one stream; calls on different streams need different workspaces.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nbody_ctx nbody_ctx;
+
+enum {
+  NB_OK = 0,
+  NB_ERR_ARG = -1,         /* invalid argument; nothing was launched */
+  NB_ERR_HIP = -2,         /* a HIP runtime call failed */
+  NB_ERR_NOMEM = -3,       /* host-side allocation failed, or workspace too small */
+  NB_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+  NB_ERR_NONFINITE = -5    /* reserved: a diagnostic found a non-finite value */
+};
+
+enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3 };
+
+/* External galaxy (Eq. 3, F_ext), G-scaled except for the halo:
+ *   Hernquist bulge      Phi_b = -G Mb / (r + ab)
+ *   Miyamoto-Nagai disk  Phi_d = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
+ *   logarithmic halo     Phi_h = vh^2 / 2 ln(r^2 + dh^2)
+ * with R^2 = x^2 + y^2 and r^2 = R^2 + z^2; a_ext = -grad(Phi_b + Phi_d + Phi_h). */
+typedef struct {
+  double Mb, ab, Md, ad, bd, vh, dh;
+} nbody_galaxy;
+
+/* A ragged batch of clusters.  All pointers are HOST pointers read during the call only. */
+typedef struct {
+  int32_t nclusters;      /* B >= 1 */
+  const int64_t* offsets; /* [B+1], offsets[0] = 0, strictly increasing (every cluster >= 1) */
+  double G;               /* gravitational constant, > 0 */
+  const double* eps;      /* [B] softening lengths, each >= 0 and finite */
+  const uint8_t* field;   /* [B] nonzero = add the galaxy field to that cluster; NULL = none */
+  nbody_galaxy galaxy;    /* used by clusters whose field flag is set */
+  int32_t prec;           /* NB_FP32 .. NB_FP64 */
+} nbody_system;
+
+/* Create a context bound to HIP device `device` (>= 0).  The context caches launch plans and
+ * tile choices; it owns a small pinned host staging area and never allocates device memory.
+ * Returns NB_ERR_ARG for a bad device or NULL out, NB_ERR_HIP if the device cannot be used. */
+int nbody_create(int device, nbody_ctx** out);
+
+/* Destroy a context (NULL is allowed).  Waits for the staging copies it issued. */
+void nbody_destroy(nbody_ctx* ctx);
+
+/* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
+ * nbody_last_error() says why).  About 40 bytes per particle plus O(B) bookkeeping.  The
+ * workspace must be 256-byte aligned; its contents are the library's between calls (the caller
+ * must not modify it while calls using it are in flight). */
+size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);
+
+/* Accelerations (Eq. 5 + external field of Eq. 3) of every particle of every cluster:
+ *   acc[i] = a_i as defined above;  pot[i] = pair potential as defined above (pot may be NULL).
+ * pos, mass: device, read.  acc, pot: device, written.  ws: device workspace of ws_bytes bytes.
+ * stream: a hipStream_t (NULL = the default stream).  Asynchronous. */
+int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass,
+                double* acc, double* pot, void* ws, size_t ws_bytes, void* stream);
+
+/* One integrator stage for every cluster b, with per-cluster coefficients (time step folded in):
+ *   vel += kick_pre[b] * acc;  pos += drift[b] * vel;  acc = A(pos);  vel += kick_post[b] * acc
+ * where A is the acceleration of nbody_accel.  kick_pre, drift, kick_post: HOST arrays [B],
+ * finite.  acc must hold A(pos) on entry (first-same-as-last).  This is the unit the
+ * continuous-batching server advances each job by; the step functions below are sequences of it.
+ * Asynchronous. */
+int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                  double* acc, const double* kick_pre, const double* drift, const double* kick_post,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps (>= 0) steps of the 2nd-order leapfrog (Sect. 3.1) in kick-drift-kick form, step dt
+ * (finite, any sign: a negative dt integrates backwards):
+ *   vel += dt/2 acc;  pos += dt vel;  acc = A(pos);  vel += dt/2 acc
+ * acc: on entry A(pos) (obtain it once with nbody_accel), on return A(pos_final).
+ * One force evaluation per step.  Asynchronous. */
+int nbody_step_leapfrog(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                        double* acc, double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps steps of the 6th-order symplectic integrator of Sect. 3.1: the symmetric composition
+ * S2(w3 h) S2(w2 h) S2(w1 h) S2(w0 h) S2(w1 h) S2(w2 h) S2(w3 h) of kick-drift-kick leapfrogs
+ * (Yoshida 1990, solution A: w1 = -1.17767998417887, w2 = 0.235573213359357,
+ * w3 = 0.784513610477560, w0 = 1 - 2(w1 + w2 + w3)), with the touching half-kicks inside one step
+ * merged: 7 drifts, 8 kicks, 7 force evaluations per step.  Same arguments as the leapfrog. */
+int nbody_step_sym6(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                    double* acc, double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream);
+
+/* Diagnostics of Sect. 5.1 per cluster, written to the DEVICE array out[B][16] (float64):
+ *   0 K = 1/2 sum m |v|^2     1 W = 1/2 sum m_i pot_i     2 Uext = sum m Phi_ext (field clusters)
+ *   3 E = K + W + Uext         4..6 P = sum m v             7..9 L = sum m x cross v
+ *   10..12 torque = sum m x cross a_ext(x) (Eq. 8)          13 M = sum m
+ *   14 0                       15 1.0 if any of the sums is not finite, else 0.0
+ * The pair potential is evaluated in the system's precision mode (use NB_FP64 for energy-error
+ * measurements).  Reductions run in FP64 in a fixed order (bitwise reproducible).
+ * Asynchronous; the non-finite flag is reported in out[b][15] (the call itself cannot see it). */
+int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* vel,
+                 const double* mass, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* nbody_last_error(void);
+
+/* ---- Tuning and instrumentation (not part of the method) ---------------------------------- */
+
+/* Pair-kernel launch shape for one precision family and cluster-size class:
+ *   prec  NB_FP32 / NB_FP32C (share a kernel), NB_FP32DS or NB_FP64
+ *   nclass 0: N_c < 2048, 1: N_c < 32768, 2: larger (the class of a batch is its largest cluster)
+ *   k     i-particles per lane (1, 2 or 4);  tile  j-records per LDS tile (64, 128 or 256)
+ *   blocks_per_cu  persistent blocks per compute unit (1..8)
+ * Returns NB_ERR_ARG for combinations that are not compiled in. */
+typedef struct {
+  int32_t k, tile, blocks_per_cu;
+} nbody_tile;
+int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
+int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);
+
+/* Per-kernel timing with HIP events recorded on the call's stream around every pair-kernel
+ * launch (enable = 1) or off (0, the default).  nbody_timing_read returns the summed duration
+ * in milliseconds and the number of timed launches since the last read, waiting for the
+ * recorded events to complete; it resets the counters. */
+int nbody_timing_enable(nbody_ctx* ctx, int enable);
+int nbody_timing_read(nbody_ctx* ctx, double* ms_total, int64_t* launches);
+
+/* Pair interactions one force evaluation of `sys` performs: sum_b N_b^2 (j = i counted). */
+int64_t nbody_interactions(const nbody_system* sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

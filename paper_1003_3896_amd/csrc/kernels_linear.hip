@@ -1,0 +1,216 @@
+// O(N) kernels of libnbody for gfx950: fused kick + drift + centre-of-mass partials, record
+// packing, and the energy / momentum diagnostics.  All are HBM-bound; one block of kBlock threads
+// handles one chunk of kChunk particles of one cluster, so per-cluster reductions never mix
+// clusters.  Every reduction runs in a fixed order (bitwise reproducible); the last block of a
+// cluster to finish (device-scope atomic counter) combines the chunk partials and resets the
+// counter for the next launch.
+#include "nb_device.h"
+
+namespace nb {
+
+enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3 };
+
+// Fixed-order tree reduction of V doubles per thread over the block; result valid in thread 0.
+template <int V>
+__device__ __forceinline__ void block_reduce(double (&val)[V], double (*sh)[kBlock]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < V; ++q) sh[q][t] = val[q];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) sh[q][t] += sh[q][t + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) val[q] = sh[q][0];
+}
+
+// Returns true in every thread of the block that finished cluster `cl` last (after its partial
+// was published by thread 0).
+__device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks) {
+  __shared__ int s_last;
+  __threadfence();
+  if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1) == nchunks - 1);
+  __syncthreads();
+  const bool last = s_last;
+  if (last) __threadfence();
+  return last;
+}
+
+// Kick (v += kick_pre a) and drift (x += drift v) of one chunk; optionally the centre-of-mass
+// partial sums of the updated positions and, in the last block of a cluster, the cluster's
+// reference point ref = sum m x / sum m.
+__global__ __launch_bounds__(kBlock) void k_update(Args a, int update, int com) {
+  __shared__ double sh[4][kBlock];
+  const Chunk ch = a.chunks[blockIdx.x];
+  const DevCluster c = a.cl[ch.cluster];
+  const int t = threadIdx.x;
+  const bool valid = t < ch.count;
+  const long long i = c.off + ch.start + t;
+  double x[3] = {0.0, 0.0, 0.0}, m = 0.0;
+  if (valid) {
+    m = a.mass[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * i + d];
+    if (update) {
+      const double kc = a.coef ? a.coef[3 * ch.cluster] : a.kick_pre;
+      const double dc = a.coef ? a.coef[3 * ch.cluster + 1] : a.drift;
+      double v[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = a.vel[3 * i + d];
+      if (a.prec == NB_FP32) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float vf = fmaf((float)kc, (float)a.acc[3 * i + d], (float)v[d]);
+          const float xf = fmaf((float)dc, vf, (float)x[d]);
+          v[d] = vf;
+          x[d] = xf;
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          v[d] = fma(kc, a.acc[3 * i + d], v[d]);
+          x[d] = fma(dc, v[d], x[d]);
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.vel[3 * i + d] = v[d];
+        a.pos[3 * i + d] = x[d];
+      }
+    }
+  }
+  if (!com) return;
+  double val[4] = {m * x[0], m * x[1], m * x[2], m};
+  block_reduce<4>(val, sh);
+  if (t == 0) a.partials[blockIdx.x] = make_double4(val[0], val[1], val[2], val[3]);
+  if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = t; q < c.nchunks; q += kBlock) {
+    const double4 p = a.partials[c.chunk0 + q];
+    tot[0] += p.x;
+    tot[1] += p.y;
+    tot[2] += p.z;
+    tot[3] += p.w;
+  }
+  __syncthreads();
+  block_reduce<4>(tot, sh);
+  if (t == 0) {
+    const double M = tot[3];
+    a.ref[ch.cluster] = M > 0.0 ? make_double4(tot[0] / M, tot[1] / M, tot[2] / M, M)
+                                : make_double4(0.0, 0.0, 0.0, 0.0);
+    a.chunk_counter[ch.cluster] = 0;
+  }
+}
+
+// Pack the j-records the pair kernel streams through LDS:
+//   NB_FP32   (x, y, z, m) rounded to FP32 (absolute coordinates)
+//   NB_FP32C  (x - ref, m) rounded to FP32
+//   NB_FP32DS hi = fl32(x - ref), lo = fl32((x - ref) - hi)   (double-single coordinates)
+//   NB_FP64   (x, y, z, m) in FP64 (absolute)
+// Also clears the pair kernel's work counter (this kernel always precedes it).
+__global__ __launch_bounds__(kBlock) void k_pack(Args a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.item_counter = 0;
+  const Chunk ch = a.chunks[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= ch.count) return;
+  const DevCluster c = a.cl[ch.cluster];
+  const long long i = c.off + ch.start + t;
+  const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2], m = a.mass[i];
+  if (a.prec == NB_FP64) {
+    a.rec64[i] = make_double4(x, y, z, m);
+  } else if (a.prec == NB_FP32) {
+    a.rec_hi[i] = make_float4((float)x, (float)y, (float)z, (float)m);
+  } else {
+    const double4 r = a.ref[ch.cluster];
+    const double dx = x - r.x, dy = y - r.y, dz = z - r.z;
+    const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
+    a.rec_hi[i] = make_float4(hx, hy, hz, (float)m);
+    if (a.prec == NB_FP32DS)
+      a.rec_lo[i] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
+  }
+}
+
+// Diagnostics of one chunk (K, W, Uext, P, L, torque, M), then per cluster in the last block.
+__global__ __launch_bounds__(kBlock) void k_energy(Args a) {
+  __shared__ double sh[14][kBlock];
+  const Chunk ch = a.chunks[blockIdx.x];
+  const DevCluster c = a.cl[ch.cluster];
+  const int t = threadIdx.x;
+  double q[14];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) q[k] = 0.0;
+  if (t < ch.count) {
+    const long long i = c.off + ch.start + t;
+    const double m = a.mass[i];
+    const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+    const double vx = a.vel[3 * i], vy = a.vel[3 * i + 1], vz = a.vel[3 * i + 2];
+    q[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    q[1] = 0.5 * m * a.pot_ws[i];
+    q[3] = m * vx;
+    q[4] = m * vy;
+    q[5] = m * vz;
+    q[6] = m * (y * vz - z * vy);
+    q[7] = m * (z * vx - x * vz);
+    q[8] = m * (x * vy - y * vx);
+    q[12] = m;
+    if (c.flags & kFlagField) {
+      double ex, ey, ez;
+      galaxy_accel(a.gal, a.G, x, y, z, ex, ey, ez);
+      q[2] = m * galaxy_potential(a.gal, a.G, x, y, z);
+      q[9] = m * (y * ez - z * ey);
+      q[10] = m * (z * ex - x * ez);
+      q[11] = m * (x * ey - y * ex);
+    }
+  }
+  block_reduce<14>(q, sh);
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < 14; ++k) a.epart[(size_t)blockIdx.x * 16 + k] = q[k];
+  }
+  if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
+  double tot[14];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) tot[k] = 0.0;
+  for (int p = t; p < c.nchunks; p += kBlock) {
+    const double* e = a.epart + (size_t)(c.chunk0 + p) * 16;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) tot[k] += e[k];
+  }
+  __syncthreads();
+  block_reduce<14>(tot, sh);
+  if (t == 0) {
+    double* o = a.eout + (size_t)ch.cluster * 16;
+    const double K = tot[0], W = tot[1], U = tot[2];
+    o[0] = K;
+    o[1] = W;
+    o[2] = U;
+    o[3] = K + W + U;
+    for (int k = 3; k < 13; ++k) o[k + 1] = tot[k];
+    o[14] = 0.0;
+    bool finite = true;
+    for (int k = 0; k < 14; ++k) finite = finite && isfinite(o[k]);
+    o[15] = finite ? 0.0 : 1.0;
+    a.chunk_counter[ch.cluster] = 0;
+  }
+}
+
+hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(a.nchunks), dim3(kBlock), 0, s, a, update ? 1 : 0, com ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Args& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(a.nchunks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const Args& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(a.nchunks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace nb

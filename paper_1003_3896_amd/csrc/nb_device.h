@@ -1,0 +1,47 @@
+// Device helpers for the gfx950 kernels of libnbody.
+#pragma once
+#include "nb_internal.h"
+
+namespace nb {
+
+// External galaxy field at (X,Y,Z) in FP64 (the F_ext term of Eq. 3):
+// Hernquist bulge + Miyamoto-Nagai disk + logarithmic halo; acceleration = -grad Phi.
+__device__ __forceinline__ void galaxy_accel(const Galaxy& g, double G, double X, double Y, double Z, double& ax,
+                                             double& ay, double& az) {
+  const double R2 = X * X + Y * Y;
+  const double r2 = R2 + Z * Z;
+  const double r = sqrt(r2);
+  const double rb = r + g.ab;
+  const double fb = r > 0.0 ? G * g.Mb / (r * rb * rb) : 0.0;  // |grad Phi_b| / r
+  const double zs = sqrt(Z * Z + g.bd * g.bd);
+  const double as = g.ad + zs;
+  const double D2 = R2 + as * as;
+  const double fd = G * g.Md / (D2 * sqrt(D2));                // (1/R) dPhi_d/dR
+  const double fz = fd * as / zs;                               // (1/z) dPhi_d/dz
+  const double fh = g.vh * g.vh / (r2 + g.dh * g.dh);           // (1/r) dPhi_h/dr
+  const double fxy = fb + fd + fh;
+  ax = -fxy * X;
+  ay = -fxy * Y;
+  az = -(fb + fz + fh) * Z;
+}
+
+__device__ __forceinline__ double galaxy_potential(const Galaxy& g, double G, double X, double Y, double Z) {
+  const double R2 = X * X + Y * Y;
+  const double r2 = R2 + Z * Z;
+  const double r = sqrt(r2);
+  const double zs = sqrt(Z * Z + g.bd * g.bd);
+  const double as = g.ad + zs;
+  return -G * g.Mb / (r + g.ab) - G * g.Md / sqrt(R2 + as * as) + 0.5 * g.vh * g.vh * log(r2 + g.dh * g.dh);
+}
+
+// 1/sqrt(x) in FP64: the hardware estimate (relative error ~2^-24) refined by one
+// third-order Newton step y' = y + y e (1/2 + 3/8 e), e = 1 - x y^2 (error O(e^3)).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  const double e = fma(-h, y, 1.0);
+  const double t = fma(0.375, e, 0.5);
+  return fma(y * e, t, y);
+}
+
+}  // namespace nb

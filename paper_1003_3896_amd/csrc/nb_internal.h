@@ -1,0 +1,87 @@
+// Internal types shared by the gfx950 kernels and the host runtime of libnbody.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Threads per block of every kernel, and particles per O(N) chunk (one per thread).
+constexpr int kBlock = 256;
+constexpr int kChunk = 256;
+
+// Precision families of the pair kernel.
+enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2 };
+
+// Per-cluster descriptor in device memory (uploaded with every call).
+struct DevCluster {
+  long long off;  // first particle of the cluster in the concatenated arrays
+  int n;          // particles
+  int flags;      // kFlagField | kFlagMaskSelf
+  double eps2;    // eps^2 in FP64
+  float eps2f;    // eps^2 rounded to FP32
+  int chunk0;     // first O(N) chunk of the cluster
+  int nchunks;    // O(N) chunks of the cluster
+  int pad;
+};
+constexpr int kFlagField = 1;     // add the galaxy field
+constexpr int kFlagMaskSelf = 2;  // eps == 0: the j = i term must be excluded explicitly
+
+// O(N) chunk: kChunk consecutive particles of one cluster.
+struct Chunk {
+  int cluster, start, count, pad;
+};
+
+// Pair work item: one i-tile (kBlock * K particles starting at i0) of one cluster.
+struct PairItem {
+  int cluster, i0;
+};
+
+struct Galaxy {
+  double Mb, ab, Md, ad, bd, vh, dh;
+};
+
+// Everything the kernels of one call need; passed by value.
+struct Args {
+  const DevCluster* cl;
+  const Chunk* chunks;
+  int nchunks;
+  const PairItem* items;
+  int nitems;
+  int* item_counter;   // dynamic work distribution of the persistent pair kernel
+  int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
+  double4* partials;   // [nchunks] CoM partial sums (sum m x, sum m y, sum m z, sum m)
+  double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
+  double* epart;       // [nchunks * 16] energy partials
+  float4* rec_hi;      // [Ntot] packed j-records (FP32 families)
+  float4* rec_lo;      // [Ntot] low parts (double-single family)
+  double4* rec64;      // [Ntot] packed j-records (FP64 family)
+  double* pot_ws;      // [Ntot] pair potential scratch for the energy pass
+  double* coef;        // [B*3] per-cluster (kick_pre, drift, kick_post), or null
+  // state
+  double* pos;
+  double* vel;
+  double* acc;
+  double* pot;
+  const double* mass;
+  double* eout;  // [B*16] energy output
+  // uniform coefficients (used when coef == null)
+  double kick_pre, drift, kick_post;
+  double G;
+  Galaxy gal;
+  int prec;  // NB_FP32 .. NB_FP64
+};
+
+struct TileCfg {
+  int k, tile, bpc;
+};
+
+// Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
+hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s);
+hipError_t launch_pack(const Args& a, hipStream_t s);
+hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
+                       hipStream_t s);
+hipError_t launch_energy(const Args& a, hipStream_t s);
+
+bool tile_supported(int family, const TileCfg& t);
+
+}  // namespace nb

@@ -1,0 +1,645 @@
+// Host runtime and C ABI of libnbody (include/nbody.h): argument validation (host only, before
+// any HIP call), launch planning for ragged batches, workspace layout, kernel sequencing of the
+// integrators, pinned staging of the per-call tables, and optional per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nbody.h"
+#include "nb_internal.h"
+
+using namespace nb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(NB_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// The 6th-order composition of Sect. 3.1 (Yoshida 1990, solution A): drift weights of the 7
+// leapfrog stages and the 8 merged kick weights.
+struct Sym6 {
+  double d[7], k[8];
+  Sym6() {
+    const double w1 = -1.17767998417887, w2 = 0.235573213359357, w3 = 0.784513610477560;
+    const double w0 = 1.0 - 2.0 * (w1 + w2 + w3);
+    const double w[7] = {w3, w2, w1, w0, w1, w2, w3};
+    for (int i = 0; i < 7; ++i) d[i] = w[i];
+    k[0] = 0.5 * w[0];
+    for (int i = 1; i < 7; ++i) k[i] = 0.5 * (w[i - 1] + w[i]);
+    k[7] = 0.5 * w[6];
+  }
+};
+const Sym6 kSym6;
+
+// Workspace layout of one system (depends on the system only, not on the tile choice).
+struct Layout {
+  size_t cl, chunks, items, coef, counters, ref, partials, epart, rec_hi, rec_lo, rec64, pot, total;
+  size_t blob;  // bytes of the uploaded prefix [cl .. counters]
+};
+
+struct Plan {
+  int B = 0;
+  long long ntot = 0;
+  int nchunks = 0;
+  int maxn = 0;
+  bool anymask = false;
+  std::vector<DevCluster> cl;
+  std::vector<Chunk> chunks;
+  Layout L{};
+};
+
+struct Slot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool used = false;
+};
+
+int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : 2; }
+int family_of(int prec) { return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ? FAM_DS : FAM_F32; }
+
+}  // namespace
+
+struct nbody_ctx {
+  int device = 0;
+  int cus = 256;
+  TileCfg tiles[3][3];
+  Slot slots[4];
+  int next_slot = 0;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<hipEvent_t> event_pool;
+  double ms_acc = 0.0;
+  int64_t launches = 0;
+  Plan plan;
+  std::vector<unsigned char> blob;
+};
+
+namespace {
+
+// RAII switch to the context's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+// Host-only validation of a system description.
+int check_system(const nbody_system* sys) {
+  if (!sys) return fail(NB_ERR_ARG, "system is NULL");
+  if (sys->nclusters < 1) return fail(NB_ERR_ARG, "nclusters must be >= 1 (got %d)", sys->nclusters);
+  if (!sys->offsets) return fail(NB_ERR_ARG, "offsets is NULL");
+  if (!sys->eps) return fail(NB_ERR_ARG, "eps is NULL");
+  if (sys->offsets[0] != 0) return fail(NB_ERR_ARG, "offsets[0] must be 0");
+  for (int b = 0; b < sys->nclusters; ++b) {
+    const long long n = sys->offsets[b + 1] - sys->offsets[b];
+    if (n < 1) return fail(NB_ERR_ARG, "cluster %d is empty or offsets decrease", b);
+    if (n > (1LL << 30)) return fail(NB_ERR_ARG, "cluster %d has %lld particles (max 2^30)", b, n);
+    const double e = sys->eps[b];
+    if (!(std::isfinite(e) && e >= 0.0)) return fail(NB_ERR_ARG, "eps[%d] must be finite and >= 0", b);
+  }
+  if (!(std::isfinite(sys->G) && sys->G > 0.0)) return fail(NB_ERR_ARG, "G must be finite and > 0");
+  if (sys->prec < NB_FP32 || sys->prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", sys->prec);
+  bool anyfield = false;
+  if (sys->field)
+    for (int b = 0; b < sys->nclusters; ++b) anyfield |= sys->field[b] != 0;
+  if (anyfield) {
+    const nbody_galaxy& g = sys->galaxy;
+    const double v[7] = {g.Mb, g.ab, g.Md, g.ad, g.bd, g.vh, g.dh};
+    for (double x : v)
+      if (!std::isfinite(x)) return fail(NB_ERR_ARG, "galaxy parameters must be finite");
+    if (g.Mb < 0 || g.Md < 0 || g.ad < 0 || g.vh < 0)
+      return fail(NB_ERR_ARG, "galaxy masses, ad and vh must be >= 0");
+    if (!(g.ab > 0 && g.bd > 0 && g.dh > 0)) return fail(NB_ERR_ARG, "galaxy ab, bd and dh must be > 0");
+  }
+  return NB_OK;
+}
+
+Layout make_layout(int B, long long ntot, int nchunks) {
+  Layout L{};
+  size_t o = 0;
+  L.cl = o;
+  o = align_up(o + sizeof(DevCluster) * B);
+  L.chunks = o;
+  o = align_up(o + sizeof(Chunk) * nchunks);
+  L.items = o;
+  o = align_up(o + sizeof(PairItem) * nchunks);  // K = 1 has as many items as there are chunks
+  L.coef = o;
+  o = align_up(o + sizeof(double) * 3 * B);
+  L.counters = o;  // [B] chunk counters + 1 item counter
+  o = align_up(o + sizeof(int) * (B + 1));
+  L.blob = o;
+  L.ref = o;
+  o = align_up(o + sizeof(double4) * B);
+  L.partials = o;
+  o = align_up(o + sizeof(double4) * nchunks);
+  L.epart = o;
+  o = align_up(o + sizeof(double) * 16 * nchunks);
+  // records: the FP32 and DS families use rec_hi (+ rec_lo), the FP64 family rec64; they share
+  L.rec_hi = o;
+  L.rec64 = o;
+  L.rec_lo = align_up(o + sizeof(float4) * ntot);
+  o = align_up(std::max(L.rec_lo + sizeof(float4) * ntot, o + sizeof(double4) * ntot));
+  L.pot = o;
+  o = align_up(o + sizeof(double) * ntot);
+  L.total = o;
+  return L;
+}
+
+// Validate the system and build the host tables.
+int build_plan(const nbody_system* sys, Plan& p) {
+  int rc = check_system(sys);
+  if (rc) return rc;
+  p.B = sys->nclusters;
+  p.cl.resize(p.B);
+  p.chunks.clear();
+  p.maxn = 0;
+  p.anymask = false;
+  for (int b = 0; b < p.B; ++b) {
+    DevCluster& c = p.cl[b];
+    c.off = sys->offsets[b];
+    c.n = (int)(sys->offsets[b + 1] - sys->offsets[b]);
+    const double e = sys->eps[b];
+    c.eps2 = e * e;
+    c.eps2f = (float)(e * e);
+    c.flags = (sys->field && sys->field[b]) ? kFlagField : 0;
+    // FP32 rounding of a tiny eps^2 to 0 would make the self term 0 * inf; mask it then too
+    const bool mask = (c.eps2 == 0.0) || (sys->prec != NB_FP64 && c.eps2f == 0.0f);
+    if (mask) c.flags |= kFlagMaskSelf;
+    p.anymask |= mask;
+    c.chunk0 = (int)p.chunks.size();
+    c.nchunks = (c.n + kChunk - 1) / kChunk;
+    for (int s = 0; s < c.n; s += kChunk) p.chunks.push_back(Chunk{b, s, std::min(kChunk, c.n - s), 0});
+    c.pad = 0;
+    p.maxn = std::max(p.maxn, c.n);
+  }
+  p.ntot = sys->offsets[p.B];
+  p.nchunks = (int)p.chunks.size();
+  p.L = make_layout(p.B, p.ntot, p.nchunks);
+  return NB_OK;
+}
+
+// Pair work items for i-tiles of kBlock*K particles, largest clusters first (ties by index).
+void make_items(const Plan& p, int K, std::vector<PairItem>& items) {
+  std::vector<int> order(p.B);
+  for (int b = 0; b < p.B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].n > p.cl[y].n; });
+  items.clear();
+  const int tile = kBlock * K;
+  for (int b : order)
+    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) items.push_back(PairItem{b, i0});
+}
+
+Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
+  Slot& s = ctx->slots[ctx->next_slot];
+  ctx->next_slot = (ctx->next_slot + 1) % 4;
+  *rc = NB_OK;
+  if (s.used) {
+    hipError_t e = hipEventSynchronize(s.ev);
+    if (e != hipSuccess) {
+      *rc = fail(NB_ERR_HIP, "staging wait: %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    s.used = false;
+  }
+  if (!s.ev && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+    *rc = fail(NB_ERR_HIP, "hipEventCreate failed");
+    return nullptr;
+  }
+  if (s.cap < bytes) {
+    if (s.host) (void)hipHostFree(s.host);
+    s.host = nullptr;
+    s.cap = 0;
+    size_t cap = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) {
+      *rc = fail(NB_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", cap);
+      return nullptr;
+    }
+    s.cap = cap;
+  }
+  return &s;
+}
+
+// Everything a call needs after validation: device tables uploaded, Args filled.
+struct Prepared {
+  Args a{};
+  TileCfg tile{};
+  int grid = 0;
+  bool centred = false;
+};
+
+int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, const double* coef3,
+            Prepared& P, hipStream_t stream) {
+  Plan& p = ctx->plan;
+  const int fam = family_of(sys->prec);
+  const TileCfg t = ctx->tiles[fam][size_class(p.maxn)];
+  std::vector<PairItem> items;
+  make_items(p, t.k, items);
+  // host blob: [clusters | chunks | items | coef | counters]
+  const Layout& L = p.L;
+  std::vector<unsigned char>& blob = ctx->blob;
+  blob.assign(L.blob, 0);
+  memcpy(blob.data() + L.cl, p.cl.data(), sizeof(DevCluster) * p.B);
+  memcpy(blob.data() + L.chunks, p.chunks.data(), sizeof(Chunk) * p.nchunks);
+  memcpy(blob.data() + L.items, items.data(), sizeof(PairItem) * items.size());
+  if (coef3) memcpy(blob.data() + L.coef, coef3, sizeof(double) * 3 * p.B);
+  int rc = NB_OK;
+  Slot* s = get_slot(ctx, L.blob, &rc);
+  if (!s) return rc;
+  memcpy(s->host, blob.data(), L.blob);
+  HIP_TRY(hipMemcpyAsync(ws, s->host, L.blob, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(s->ev, stream));
+  s->used = true;
+
+  char* w = static_cast<char*>(ws);
+  Args& a = P.a;
+  a.cl = reinterpret_cast<const DevCluster*>(w + L.cl);
+  a.chunks = reinterpret_cast<const Chunk*>(w + L.chunks);
+  a.nchunks = p.nchunks;
+  a.items = reinterpret_cast<const PairItem*>(w + L.items);
+  a.nitems = (int)items.size();
+  a.chunk_counter = reinterpret_cast<int*>(w + L.counters);
+  a.item_counter = reinterpret_cast<int*>(w + L.counters) + p.B;
+  a.partials = reinterpret_cast<double4*>(w + L.partials);
+  a.ref = reinterpret_cast<double4*>(w + L.ref);
+  a.epart = reinterpret_cast<double*>(w + L.epart);
+  a.rec_hi = reinterpret_cast<float4*>(w + L.rec_hi);
+  a.rec_lo = reinterpret_cast<float4*>(w + L.rec_lo);
+  a.rec64 = reinterpret_cast<double4*>(w + L.rec64);
+  a.pot_ws = reinterpret_cast<double*>(w + L.pot);
+  a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
+  a.G = sys->G;
+  a.gal = Galaxy{sys->galaxy.Mb, sys->galaxy.ab, sys->galaxy.Md, sys->galaxy.ad,
+                 sys->galaxy.bd, sys->galaxy.vh, sys->galaxy.dh};
+  a.prec = sys->prec;
+  P.tile = t;
+  P.grid = std::max(1, std::min(a.nitems, ctx->cus * t.bpc));
+  P.centred = sys->prec == NB_FP32C || sys->prec == NB_FP32DS;
+  (void)ws_bytes;
+  return NB_OK;
+}
+
+hipEvent_t pool_event(nbody_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int pair(nbody_ctx* ctx, const Prepared& P, bool potmode, bool kick, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    e0 = pool_event(ctx);
+    e1 = pool_event(ctx);
+    if (!e0 || !e1) return fail(NB_ERR_HIP, "event creation failed");
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  hipError_t e = launch_pair(P.a, P.tile, P.grid, ctx->plan.anymask, potmode, kick, s);
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "pair kernel launch: %s", hipGetErrorString(e));
+  if (ctx->timing) {
+    HIP_TRY(hipEventRecord(e1, s));
+    ctx->pending.emplace_back(e0, e1);
+  }
+  return NB_OK;
+}
+
+// One force evaluation of the current positions, optionally preceded by kick+drift and
+// followed by a kick (the substep).  Kernel sequence: [update+CoM] -> pack -> pair.
+int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, hipStream_t s) {
+  hipError_t e;
+  if (update || P.centred) {
+    e = launch_update(P.a, update, P.centred, s);
+    if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
+  }
+  e = launch_pack(P.a, s);
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "pack kernel launch: %s", hipGetErrorString(e));
+  return pair(ctx, P, potmode, kick, s);
+}
+
+int check_ptr(const void* p, const char* name) {
+  if (!p) return fail(NB_ERR_ARG, "%s is NULL", name);
+  if (!aligned(p, 8)) return fail(NB_ERR_ARG, "%s is not 8-byte aligned", name);
+  return NB_OK;
+}
+
+int check_ws(const Plan& p, const void* ws, size_t ws_bytes) {
+  if (!ws) return fail(NB_ERR_ARG, "workspace is NULL");
+  if (!aligned(ws, kAlign)) return fail(NB_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.L.total)
+    return fail(NB_ERR_ARG, "workspace too small: %zu bytes given, %zu needed", ws_bytes, p.L.total);
+  return NB_OK;
+}
+
+// Common validation of the state arrays (distinct, non-overlapping, aligned).
+int check_state(const Plan& p, const void* pos, const void* vel, const void* mass, const void* acc, const void* ws,
+                size_t ws_bytes) {
+  int rc;
+  if ((rc = check_ptr(pos, "pos")) || (rc = check_ptr(mass, "mass")) || (rc = check_ptr(acc, "acc"))) return rc;
+  if (vel && (rc = check_ptr(vel, "vel"))) return rc;
+  if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+  const size_t n3 = 24 * (size_t)p.ntot, n1 = 8 * (size_t)p.ntot;
+  struct R {
+    const void* p;
+    size_t n;
+    const char* name;
+    bool written;
+  } r[5] = {{pos, n3, "pos", vel != nullptr},
+            {vel, n3, "vel", true},
+            {mass, n1, "mass", false},
+            {acc, n3, "acc", true},
+            {ws, p.L.total, "workspace", true}};
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j) {
+      if (!r[i].p || !r[j].p) continue;
+      if (!r[i].written && !r[j].written) continue;
+      if (overlap(r[i].p, r[i].n, r[j].p, r[j].n))
+        return fail(NB_ERR_ARG, "%s and %s overlap", r[i].name, r[j].name);
+    }
+  return NB_OK;
+}
+
+void default_tiles(nbody_ctx* ctx) {
+  for (int f = 0; f < 3; ++f)
+    for (int c = 0; c < 3; ++c) ctx->tiles[f][c] = TileCfg{1, f == FAM_F32 ? 256 : 128, 4};
+}
+
+int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass, double* acc,
+              double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream, bool sym6) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = build_plan(sys, ctx->plan);
+  if (rc) return rc;
+  if ((rc = check_state(ctx->plan, pos, vel, mass, acc, ws, ws_bytes))) return rc;
+  if (!vel) return fail(NB_ERR_ARG, "vel is NULL");
+  if (!std::isfinite(dt)) return fail(NB_ERR_ARG, "dt must be finite");
+  if (nsteps < 0) return fail(NB_ERR_ARG, "nsteps must be >= 0");
+  if (nsteps == 0) return NB_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Prepared P;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, nullptr, P, s))) return rc;
+  P.a.pos = pos;
+  P.a.vel = vel;
+  P.a.acc = acc;
+  P.a.mass = mass;
+  P.a.pot = nullptr;
+  for (int32_t step = 0; step < nsteps; ++step) {
+    const int stages = sym6 ? 7 : 1;
+    for (int k = 0; k < stages; ++k) {
+      P.a.kick_pre = (sym6 ? kSym6.k[k] : 0.5) * dt;
+      P.a.drift = (sym6 ? kSym6.d[k] : 1.0) * dt;
+      const bool last = k == stages - 1;
+      P.a.kick_post = last ? (sym6 ? kSym6.k[7] : 0.5) * dt : 0.0;
+      if ((rc = evaluate(ctx, P, true, false, last, s))) return rc;
+    }
+  }
+  return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nbody_last_error(void) { return g_err.c_str(); }
+
+int nbody_create(int device, nbody_ctx** out) {
+  if (!out) return fail(NB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (device < 0) return fail(NB_ERR_ARG, "device must be >= 0");
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device >= count) return fail(NB_ERR_ARG, "device %d does not exist (%d devices)", device, count);
+  nbody_ctx* ctx = new (std::nothrow) nbody_ctx();
+  if (!ctx) return fail(NB_ERR_NOMEM, "context allocation failed");
+  ctx->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    ctx->cus = cus;
+  default_tiles(ctx);
+  *out = ctx;
+  return NB_OK;
+}
+
+void nbody_destroy(nbody_ctx* ctx) {
+  if (!ctx) return;
+  for (Slot& s : ctx->slots) {
+    if (s.used && s.ev) (void)hipEventSynchronize(s.ev);
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    if (s.host) (void)hipHostFree(s.host);
+  }
+  for (auto& pr : ctx->pending) {
+    (void)hipEventSynchronize(pr.second);
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys) {
+  (void)ctx;
+  Plan p;
+  if (build_plan(sys, p)) return 0;
+  return p.L.total;
+}
+
+int64_t nbody_interactions(const nbody_system* sys) {
+  if (check_system(sys)) return -1;
+  int64_t tot = 0;
+  for (int b = 0; b < sys->nclusters; ++b) {
+    const int64_t n = sys->offsets[b + 1] - sys->offsets[b];
+    tot += n * n;
+  }
+  return tot;
+}
+
+int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
+                double* pot, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = build_plan(sys, ctx->plan);
+  if (rc) return rc;
+  if ((rc = check_state(ctx->plan, pos, nullptr, mass, acc, ws, ws_bytes))) return rc;
+  if (pot) {
+    if ((rc = check_ptr(pot, "pot"))) return rc;
+    const size_t n1 = 8 * (size_t)ctx->plan.ntot, n3 = 3 * n1;
+    if (overlap(pot, n1, pos, n3) || overlap(pot, n1, acc, n3) || overlap(pot, n1, mass, n1) ||
+        overlap(pot, n1, ws, ctx->plan.L.total))
+      return fail(NB_ERR_ARG, "pot overlaps another buffer");
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Prepared P;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, nullptr, P, s))) return rc;
+  P.a.pos = const_cast<double*>(pos);
+  P.a.mass = mass;
+  P.a.acc = acc;
+  P.a.pot = pot;
+  P.a.vel = nullptr;
+  return evaluate(ctx, P, false, pot != nullptr, false, s);
+}
+
+int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                  double* acc, const double* kick_pre, const double* drift, const double* kick_post, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = build_plan(sys, ctx->plan);
+  if (rc) return rc;
+  if ((rc = check_state(ctx->plan, pos, vel, mass, acc, ws, ws_bytes))) return rc;
+  if (!vel) return fail(NB_ERR_ARG, "vel is NULL");
+  if (!kick_pre || !drift || !kick_post) return fail(NB_ERR_ARG, "coefficient arrays must not be NULL");
+  const int B = ctx->plan.B;
+  std::vector<double> coef(3 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    if (!std::isfinite(kick_pre[b]) || !std::isfinite(drift[b]) || !std::isfinite(kick_post[b]))
+      return fail(NB_ERR_ARG, "coefficients of cluster %d are not finite", b);
+    coef[3 * b] = kick_pre[b];
+    coef[3 * b + 1] = drift[b];
+    coef[3 * b + 2] = kick_post[b];
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Prepared P;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, coef.data(), P, s))) return rc;
+  P.a.pos = pos;
+  P.a.vel = vel;
+  P.a.acc = acc;
+  P.a.mass = mass;
+  P.a.pot = nullptr;
+  return evaluate(ctx, P, true, false, true, s);
+}
+
+int nbody_step_leapfrog(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                        double* acc, double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream) {
+  return run_steps(ctx, sys, pos, vel, mass, acc, dt, nsteps, ws, ws_bytes, stream, false);
+}
+
+int nbody_step_sym6(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                    double* acc, double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream) {
+  return run_steps(ctx, sys, pos, vel, mass, acc, dt, nsteps, ws, ws_bytes, stream, true);
+}
+
+int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* vel, const double* mass,
+                 double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = build_plan(sys, ctx->plan);
+  if (rc) return rc;
+  // out plays the role of the written array in the overlap checks
+  if ((rc = check_ptr(out, "out"))) return rc;
+  if ((rc = check_ptr(vel, "vel"))) return rc;
+  if ((rc = check_state(ctx->plan, pos, nullptr, mass, vel, ws, ws_bytes))) return rc;
+  const size_t no = 16 * 8 * (size_t)ctx->plan.B, n3 = 24 * (size_t)ctx->plan.ntot;
+  if (overlap(out, no, pos, n3) || overlap(out, no, vel, n3) || overlap(out, no, mass, n3 / 3) ||
+      overlap(out, no, ws, ctx->plan.L.total))
+    return fail(NB_ERR_ARG, "out overlaps another buffer");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Prepared P;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, nullptr, P, s))) return rc;
+  P.a.pos = const_cast<double*>(pos);
+  P.a.vel = const_cast<double*>(vel);
+  P.a.mass = mass;
+  P.a.acc = nullptr;
+  P.a.pot = P.a.pot_ws;
+  P.a.eout = out;
+  if ((rc = evaluate(ctx, P, false, true, false, s))) return rc;
+  hipError_t e = launch_energy(P.a, s);
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "energy kernel launch: %s", hipGetErrorString(e));
+  return NB_OK;
+}
+
+int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
+  if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
+  TileCfg t{tile.k, tile.tile, tile.blocks_per_cu};
+  const int fam = family_of(prec);
+  if (!tile_supported(fam, t))
+    return fail(NB_ERR_ARG, "tile (k=%d, tile=%d, blocks_per_cu=%d) is not compiled in", t.k, t.tile, t.bpc);
+  ctx->tiles[fam][nclass] = t;
+  return NB_OK;
+}
+
+int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile) {
+  if (!ctx || !tile) return fail(NB_ERR_ARG, "NULL argument");
+  if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
+  if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
+  const TileCfg& t = ctx->tiles[family_of(prec)][nclass];
+  tile->k = t.k;
+  tile->tile = t.tile;
+  tile->blocks_per_cu = t.bpc;
+  return NB_OK;
+}
+
+int nbody_timing_enable(nbody_ctx* ctx, int enable) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  ctx->timing = enable != 0;
+  return NB_OK;
+}
+
+int nbody_timing_read(nbody_ctx* ctx, double* ms_total, int64_t* launches) {
+  if (!ctx || !ms_total || !launches) return fail(NB_ERR_ARG, "NULL argument");
+  DeviceGuard g(ctx->device);
+  for (auto& pr : ctx->pending) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    ctx->ms_acc += ms;
+    ctx->launches += 1;
+    ctx->event_pool.push_back(pr.first);
+    ctx->event_pool.push_back(pr.second);
+  }
+  ctx->pending.clear();
+  *ms_total = ctx->ms_acc;
+  *launches = ctx->launches;
+  ctx->ms_acc = 0.0;
+  ctx->launches = 0;
+  return NB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every function that
+include/nbody.h declares, and rejects invalid systems before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1003_3896_amd import inputs, nbody
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "nbody.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for required in ("nbody_accel", "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_create",
+                     "nbody_destroy", "nbody_workspace_bytes", "nbody_substep", "nbody_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nbody.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(nbody.EXPORTS) | {"nbody_set_tile", "nbody_get_tile"}
+
+
+def test_workspace_bytes_and_interactions():
+    b = inputs.c4(B=6, lo=256, hi=4096)
+    s = nbody.system_from_batch(b)
+    ws = nbody.nbody_workspace_bytes(None, s)
+    assert ws >= 40 * b.n and ws % 256 == 0
+    assert nbody.nbody_interactions(s) == b.interactions_per_eval()
+    # workspace does not depend on precision beyond the record area bound
+    for p in ("fp32", "fp32c", "fp64"):
+        assert nbody.nbody_workspace_bytes(None, s.with_prec(p)) == ws
+
+
+@pytest.mark.parametrize("bad", [
+    dict(offsets=[0, 10, 5], eps=[0.1, 0.1]),            # decreasing
+    dict(offsets=[0, 10, 10], eps=[0.1, 0.1]),           # empty cluster
+    dict(offsets=[1, 10], eps=[0.1]),                    # offsets[0] != 0
+    dict(offsets=[0, 10], eps=[-1.0]),                   # negative eps
+    dict(offsets=[0, 10], eps=[float("nan")]),           # nan eps
+    dict(offsets=[0, 10], eps=[0.1], G=0.0),             # G <= 0
+    dict(offsets=[0, 10], eps=[0.1], G=float("inf")),    # G inf
+    dict(offsets=[0, 10], eps=[0.1], prec=7),            # unknown mode
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.0, 0.7, 12.0)),  # bd = 0
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, float("nan"))),
+])
+def test_invalid_systems_rejected_on_host(bad):
+    s = nbody.System(**bad)
+    with pytest.raises(nbody.NBodyError) as ei:
+        nbody.nbody_workspace_bytes(None, s)
+    assert ei.value.code == nbody.NB_ERR_ARG
+    assert nbody.nbody_interactions(s) == -1
+
+
+def test_null_context_rejected():
+    s = nbody.System([0, 4], [0.1])
+    for fn, args in ((nbody.nbody_accel, (None, s, 8, 8, 8, None, 256, 1 << 20, 0)),
+                     (nbody.nbody_step_leapfrog, (None, s, 8, 8, 8, 8, 0.1, 1, 256, 1 << 20, 0)),
+                     (nbody.nbody_step_sym6, (None, s, 8, 8, 8, 8, 0.1, 1, 256, 1 << 20, 0)),
+                     (nbody.nbody_energy, (None, s, 8, 8, 8, 8, 256, 1 << 20, 0))):
+        with pytest.raises(nbody.NBodyError) as ei:
+            fn(*args)
+        assert ei.value.code == nbody.NB_ERR_ARG
+        assert "context" in str(ei.value)
+    with pytest.raises(nbody.NBodyError):
+        nbody.nbody_create(-1)
+
+
+def test_oracle_and_library_share_nothing():
+    """The HIP library and the oracle are independent builds: neither links or names the other."""
+    import oracle
+    src_dir = os.path.join(ROOT, "paper_1003_3896_amd")
+    for dirpath, _, files in os.walk(src_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "nbody_oracle" not in txt and "liboracle" not in txt, f
+    osrc = open(os.path.join(ROOT, "oracle", "nbody_oracle.c")).read()
+    assert "nb_internal" not in osrc and "nbody.h" not in osrc

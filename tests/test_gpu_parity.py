@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import TOL, TOL_MEDIAN, make_sim, oracle_reference, rel_errors, stats, torch_dev
+from paper_1003_3896_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged_batch(seed=7, sizes=(1, 2, 3, 255, 256, 257, 700, 1000), field_every=3, eps=1e-3):
+    cl = []
+    for c, n in enumerate(sizes):
+        p, v, m = inputs.plummer(n, seed * 100 + c, salpeter=(c % 2 == 1))
+        fld = (c % field_every == 0)
+        if fld:
+            p, v = inputs.on_orbit(p, v)
+        cl.append(inputs.single(p, v, m, eps, fld))
+    return inputs.concat(cl)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c", "fp32"])
+def test_accel_single_cluster(prec):
+    torch_dev()
+    p, v, m = inputs.plummer(1000, 1234)
+    b = inputs.single(p, v, m, 1e-3)
+    sim = make_sim(b, prec)
+    a = sim.accel().cpu().numpy()
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    print("\n[accel %s N=1000] %s" % (prec, stats(err)), flush=True)
+    if prec in TOL:
+        assert err.max() <= TOL[prec]
+    if prec in TOL_MEDIAN:
+        assert np.median(err) <= TOL_MEDIAN[prec]
+    assert np.all(np.isfinite(a))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c"])
+def test_accel_ragged_batch_with_field(prec):
+    torch_dev()
+    b = _ragged_batch()
+    sim = make_sim(b, prec)
+    a = sim.accel().cpu().numpy()
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    print("\n[ragged %s] %s" % (prec, stats(err)), flush=True)
+    if prec in TOL:
+        assert err.max() <= TOL[prec]
+    assert np.median(err) <= TOL_MEDIAN[prec]
+    # the single-particle cluster without field feels exactly nothing
+    sizes = np.diff(b.offsets)
+    for c in np.nonzero(sizes == 1)[0]:
+        if not b.field[c]:
+            assert np.all(a[b.offsets[c]] == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds"])
+def test_zero_softening_masks_self_term(prec):
+    torch_dev()
+    p, v, m = inputs.uniform_box(300, 9)
+    b = inputs.single(p, v, m, 0.0)
+    sim = make_sim(b, prec)
+    a = sim.accel(pot=True).cpu().numpy()
+    pot = sim.pot.cpu().numpy()
+    ref, scale, rpot = oracle_reference(b, want_pot=True)
+    err = rel_errors(a, ref, scale)
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(pot))
+    assert err.max() <= TOL[prec]
+    assert np.abs(pot - rpot).max() <= (1e-13 if prec == "fp64" else 2e-6) * np.abs(rpot).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds"])
+def test_potential(prec):
+    torch_dev()
+    b = _ragged_batch(seed=3)
+    sim = make_sim(b, prec)
+    sim.accel(pot=True)
+    pot = sim.pot.cpu().numpy()
+    _, _, rpot = oracle_reference(b, want_pot=True)
+    rel = np.abs(pot - rpot) / np.maximum(np.abs(rpot), 1e-300)
+    print("\n[pot %s] max rel %.3e" % (prec, rel.max()), flush=True)
+    sizes = np.diff(b.offsets)
+    ok = np.repeat(sizes > 1, sizes)
+    assert rel[ok].max() <= (1e-13 if prec == "fp64" else 1e-6)
+    assert np.all(pot[~ok] == 0)
+
+
+def test_energy_fp64_matches_oracle():
+    torch_dev()
+    b = _ragged_batch(seed=5)
+    sim = make_sim(b, "fp64")
+    out = sim.energy().cpu().numpy()
+    for c in range(b.B):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        ref = oracle.energy(b.pos[s:e], b.vel[s:e], b.mass[s:e], b.G, b.eps[c], bool(b.field[c]), b.galaxy)
+        scale = np.abs(ref[:4]).max()
+        assert np.abs(out[c, :4] - ref[:4]).max() <= 1e-13 * scale + 1e-300
+        assert np.abs(out[c, 4:14] - ref[4:14]).max() <= 1e-13 * (np.abs(ref[4:14]).max() + 1e-300)
+        assert out[c, 15] == 0.0
+
+
+def test_energy_flags_nonfinite():
+    torch_dev()
+    p, v, m = inputs.plummer(300, 2)
+    v[17, 1] = np.inf
+    b = inputs.concat([inputs.single(p, v, m, 1e-3), inputs.single(*inputs.plummer(100, 3), 1e-3)])
+    sim = make_sim(b, "fp64")
+    out = sim.energy().cpu().numpy()
+    assert out[0, 15] == 1.0 and out[1, 15] == 0.0
+
+
+def test_leapfrog_trajectory_c1_fp64():
+    """Plummer N=1024, eps=1e-3, 100 KDK steps of dt=1/1024 in FP64: positions agree with the
+    oracle to 1e-10 relative, and the relative energy error matches the oracle's."""
+    torch_dev()
+    b = inputs.c1()
+    sim = make_sim(b, "fp64")
+    e0 = oracle.energy(b.pos, b.vel, b.mass, 1.0, 1e-3)[3]
+    sim.accel()
+    sim.step("leapfrog", 1.0 / 1024, 100)
+    pos = sim.pos.cpu().numpy()
+    vel = sim.vel.cpu().numpy()
+    acc0 = oracle.total_accel(b.pos, b.mass, 1.0, 1e-3)
+    rp, rv, ra = oracle.step(b.pos, b.vel, b.mass, acc0, 1.0 / 1024, 100, "leapfrog", 1.0, 1e-3)
+    rel = np.abs(pos - rp).max() / np.abs(rp).max()
+    print("\n[C1 trajectory] max rel pos diff %.3e" % rel, flush=True)
+    assert rel <= 1e-10
+    de_gpu = abs(oracle.energy(pos, vel, b.mass, 1.0, 1e-3)[3] - e0) / abs(e0)
+    de_ref = abs(oracle.energy(rp, rv, b.mass, 1.0, 1e-3)[3] - e0) / abs(e0)
+    print("[C1 energy] |dE/E0| gpu %.3e oracle %.3e" % (de_gpu, de_ref), flush=True)
+    assert abs(de_gpu - de_ref) <= 1e-3 * de_ref + 1e-13
+    a = sim.acc.cpu().numpy()
+    ref, scale = oracle_reference(inputs.single(pos, vel, b.mass, 1e-3))
+    assert rel_errors(a, ref, scale).max() <= TOL["fp64"]
+
+
+def test_sym6_trajectory_with_field_fp64():
+    torch_dev()
+    b = _ragged_batch(seed=11, sizes=(130, 300), field_every=1, eps=1e-2)
+    sim = make_sim(b, "fp64")
+    sim.accel()
+    dt = 1.0 / 256
+    sim.step("sym6", dt, 6)
+    pos = sim.pos.cpu().numpy()
+    for c in range(b.B):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        a0 = oracle.total_accel(b.pos[s:e], b.mass[s:e], 1.0, b.eps[c], True)
+        rp, rv, _ = oracle.step(b.pos[s:e], b.vel[s:e], b.mass[s:e], a0, dt, 6, "sym6", 1.0, b.eps[c], True)
+        assert np.abs(pos[s:e] - rp).max() <= 1e-10 * np.abs(rp).max()
+
+
+def test_substep_per_cluster_coefficients():
+    torch_dev()
+    b = _ragged_batch(seed=13, sizes=(64, 200, 333))
+    sim = make_sim(b, "fp64")
+    sim.accel()
+    kp = np.array([0.01, -0.003, 0.0])
+    dr = np.array([0.02, 0.005, 0.01])
+    kq = np.array([0.0, 0.004, 0.01])
+    sim.substep(kp, dr, kq)
+    pos = sim.pos.cpu().numpy()
+    vel = sim.vel.cpu().numpy()
+    for c in range(b.B):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        a0 = oracle.total_accel(b.pos[s:e], b.mass[s:e], 1.0, b.eps[c], bool(b.field[c]))
+        v = b.vel[s:e] + kp[c] * a0
+        x = b.pos[s:e] + dr[c] * v
+        a1 = oracle.total_accel(x, b.mass[s:e], 1.0, b.eps[c], bool(b.field[c]))
+        v = v + kq[c] * a1
+        assert np.abs(pos[s:e] - x).max() <= 1e-14 * np.abs(x).max()
+        assert np.abs(vel[s:e] - v).max() <= 1e-12 * np.abs(v).max()
+
+
+def test_deterministic_and_alone_equals_in_batch():
+    torch_dev()
+    b = _ragged_batch(seed=17)
+    sim = make_sim(b, "fp32ds")
+    a1 = sim.accel().cpu().numpy().copy()
+    a2 = sim.accel().cpu().numpy()
+    assert np.array_equal(a1, a2)
+    for c in (4, 7):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        alone = inputs.single(b.pos[s:e], b.vel[s:e], b.mass[s:e], b.eps[c], bool(b.field[c]))
+        sa = make_sim(alone, "fp32ds")
+        assert np.array_equal(sa.accel().cpu().numpy(), a1[s:e])
+
+
+def test_full_size_c3_sampled_rows():
+    """N = 262144 (the benchmark's workload) in the benchmark's launch shape: sampled rows checked
+    one by one against the oracle, plus momentum conservation over all particles."""
+    torch_dev()
+    b = inputs.c3()
+    for prec in ("fp32ds", "fp32c", "fp64"):
+        sim = make_sim(b, prec)
+        a = sim.accel().cpu().numpy()
+        rows = [(0, 64), (131072 - 32, 131072 + 32), (262144 - 64, 262144)]
+        errs = []
+        for r0, r1 in rows:
+            ref, absa = oracle.accel(b.pos, b.mass, 1.0, 1e-4, rows=(r0, r1), want_abs=True)
+            errs.append(rel_errors(a[r0:r1], ref, absa))
+        err = np.concatenate(errs)
+        print("\n[C3 %s sampled] %s" % (prec, stats(err)), flush=True)
+        if prec in TOL:
+            assert err.max() <= TOL[prec]
+        assert np.median(err) <= TOL_MEDIAN[prec]
+        mom = np.abs((b.mass[:, None] * a).sum(0)).max() / (b.mass[:, None] * np.abs(a)).sum()
+        assert mom < (1e-12 if prec == "fp64" else 1e-6)
+        sim.close()
