@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct-summation hot path on one MI355X.
+
+Default workload: a single Plummer cluster of N = 262144 equal masses (eps = 1e-4, no external
+field) advanced by the kick-drift-kick leapfrog with dt = 2^-11, pair arithmetic in FP32 with
+double-single coordinates and FP64-folded tile sums (mode fp32ds).  One "step" = one leapfrog step
+= one full force evaluation (N^2 pair interactions, j = i counted as the paper counts N^2) plus
+the O(N) kick/drift/pack kernels.  Throughput is pair interactions per second of the whole step.
+
+Prints ONE JSON line.  Besides the contract fields it carries:
+  roofline      the pair kernel (dominant, >99% of the step) against the FP32 vector peak, with
+                its duration measured by HIP events recorded around every pair-kernel launch on
+                the stream the kernel runs on, over the timed region;
+  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample of the same
+                workload (a block of rows against all N sources);
+  modes         the same step timed in the other precision modes.
+Other workloads (--workload c1|c2|c4) run their own configurations.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 20  # the paper's convention for one pair force (Sect. 4.1)
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU, 2.4 GHz)
+PEAK_FP64_TFLOPS = 78.6
+METRIC = "G pair-interactions/s & %FP32 VALU peak; batched p50/p99 job latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_1003_3896_amd import inputs
+    if name == "c1":
+        return inputs.c1(), "fp64"
+    if name == "c2":
+        return inputs.c2(), "fp32ds"
+    if name == "c3":
+        return inputs.c3(), "fp32ds"
+    return inputs.c4(), "fp32ds"
+
+
+def traffic_from_profile(prec):
+    """HBM bytes per pair-kernel launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE calibrated against a plain copy), or None if the kernel source has changed since
+    the counters were taken or no summary exists for this mode."""
+    path = os.path.join(ROOT, "profiles", "pair_%s_plummer262144.md" % prec)
+    src = os.path.join(ROOT, "paper_1003_3896_amd", "csrc", "pair_kernel.h")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256") != h:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(sim, integrator, dt, steps, warmup, torch):
+    from paper_1003_3896_amd import nbody
+    sim.accel()
+    if warmup:
+        sim.step(integrator, dt, warmup)
+    torch.cuda.synchronize()
+    nbody.nbody_timing_read(sim.ctx)  # drop anything recorded so far
+    nbody.nbody_timing_enable(sim.ctx, True)
+    t0 = time.perf_counter()
+    sim.step(integrator, dt, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nbody.nbody_timing_enable(sim.ctx, False)
+    kms, nlaunch = nbody.nbody_timing_read(sim.ctx)
+    return t1 - t0, kms, nlaunch
+
+
+def cpu_baseline(batch, pos_all, target_s, a_gpu):
+    """Time the FP64 oracle on a block of rows of the first cluster against all of its sources, at
+    the positions the GPU run ended with (so the same rows double as a parity sample)."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    n = int(batch.offsets[1])
+    pos, mass, eps = pos_all[:n], batch.mass[:n], float(batch.eps[0])
+    probe = max(1, min(n, 16))
+    t0 = time.perf_counter()
+    oracle.accel(pos, mass, batch.G, eps, rows=(0, probe))
+    tp = max(time.perf_counter() - t0, 1e-6)
+    rows = int(max(probe, min(n, probe * target_s / tp)))
+    t0 = time.perf_counter()
+    ref, absa = oracle.accel(pos, mass, batch.G, eps, rows=(0, rows), want_abs=True)
+    el = time.perf_counter() - t0
+    inter = rows * n
+    if batch.field[0]:
+        ae, _ = oracle.ext_field(pos[:rows], batch.G, batch.galaxy)
+        ref = ref + ae
+        absa = absa + np.linalg.norm(ae, axis=1)
+    err = np.linalg.norm(a_gpu[:rows] - ref, axis=1) / absa
+    return {
+        "value": inter / el / 1e9,
+        "unit": "G pair-interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "rows [0,%d) of the first cluster (N=%d) against all its sources, one FP64 force evaluation, "
+                  "%.1f s" % (rows, n, el),
+    }, {"rows": rows, "max": float(err.max()), "median": float(np.median(err))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU split is not part of this build "
+              "(asked for --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1003_3896_amd import inputs, nbody
+
+    torch.cuda.set_device(0)
+    batch, prec = workload(args.workload)
+    prec = args.prec or prec
+    integrator = batch.meta["integrator"]
+    dt = batch.meta["dt"]
+    evals_per_step = 1 if integrator == "leapfrog" else 7
+    inter_per_eval = batch.interactions_per_eval()
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    sim = nbody.Simulation(batch, prec)
+    wall, kms, nlaunch = time_steps(sim, integrator, dt, args.steps, args.warmup, torch)
+    inter = inter_per_eval * evals_per_step * args.steps
+    value = inter / wall / 1e9
+    pair_ms = kms / max(nlaunch, 1)
+    achieved = FLOPS_PER_INTERACTION * inter_per_eval / (pair_ms * 1e-3) / 1e12
+    fam_peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": fam_peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / fam_peak, 4),
+        "traffic": traffic_from_profile(prec),
+        "kernel": "pair (%s)" % prec,
+        "kernel_ms": round(pair_ms, 4),
+        "launches": nlaunch,
+        "flops_per_interaction": FLOPS_PER_INTERACTION,
+        "interactions_per_launch": inter_per_eval,
+    }
+    a_gpu = sim.acc.cpu().numpy()
+    pos_final = sim.pos.cpu().numpy()
+    sim.close()
+
+    modes = {}
+    if not args.no_modes and args.workload == "c3":
+        for m in ("fp32c", "fp32", "fp64"):
+            if m == prec:
+                continue
+            s2 = nbody.Simulation(batch, m)
+            w2, k2, n2 = time_steps(s2, integrator, dt, max(2, args.steps // 6), 1, torch)
+            st = max(2, args.steps // 6)
+            modes[m] = {"G_interactions_per_s": round(inter_per_eval * st / w2 / 1e9, 2),
+                        "pair_kernel_ms": round(k2 / max(n2, 1), 4)}
+            s2.close()
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic (seeded Plummer initial conditions)",
+        "config": {
+            "workload": batch.meta.get("name", args.workload),
+            "n_particles": batch.n,
+            "clusters": batch.B,
+            "integrator": integrator,
+            "dt": dt,
+            "eps": float(batch.eps[0]),
+            "precision_mode": prec,
+            "force_evals_per_step": evals_per_step,
+        },
+        "pct_fp32_valu_peak": round(100 * value * 1e9 * FLOPS_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12), 2),
+        "roofline": roofline,
+    }
+    if modes:
+        result["modes"] = modes
+    if not args.no_cpu_baseline:
+        cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
+        result["cpu_baseline"] = cb
+        result["parity_sample"] = parity
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,12 +152,17 @@ const char* nbody_last_error(void);
 
 /* Pair-kernel launch shape for one precision family and cluster-size class:
  *   prec  NB_FP32 / NB_FP32C (share a kernel), NB_FP32DS or NB_FP64
- *   nclass 0: N_c < 2048, 1: N_c < 32768, 2: larger (the class of a batch is its largest cluster)
- *   k     i-particles per lane (1, 2 or 4);  tile  j-records per LDS tile (64, 128 or 256)
+ *   nclass 0: largest cluster < 2048 particles, 1: < 32768, 2: larger
+ *   k     i-particles per lane; waves_per_group  wavefronts sharing the same i-particles, each
+ *         taking 1/waves_per_group of every j-tile; (k, waves_per_group) in {(1,1), (1,2), (1,4),
+ *         (2,2), (2,4)}; one work item covers 256 k / waves_per_group particles
+ *   tile  j-records per LDS tile (128 or 256); FP32 partial sums are folded into FP64 after every
+ *         tile/waves_per_group terms, so tile and waves_per_group change the last bits of FP32-mode
+ *         results while k and blocks_per_cu never do
  *   blocks_per_cu  persistent blocks per compute unit (1..8)
  * Returns NB_ERR_ARG for combinations that are not compiled in. */
 typedef struct {
-  int32_t k, tile, blocks_per_cu;
+  int32_t k, waves_per_group, tile, blocks_per_cu;
 } nbody_tile;
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);

@@ -1,0 +1,120 @@
+"""Tile-shape autotuner for the pair kernel.
+
+For one workload (a ragged batch) and precision mode, time every compiled-in launch shape
+(k i-particles per lane, waves per i-group, LDS tile, blocks per CU) with the library's own
+event timing around the pair kernel, and keep the fastest shape whose accelerations stay within
+the mode's error bound of the library's FP64 evaluation of the same state (sampled rows).  The
+winners are cached as JSON per (architecture, precision family, cluster-size class) and applied
+to a context with ``apply``.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import nbody
+
+SHAPES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4)]
+TILES = [128, 256]
+BLOCKS_PER_CU = [2, 4, 8]
+FAMILY = {"fp32": "f32", "fp32c": "f32", "fp32ds": "ds", "fp64": "f64"}
+# error bound a shape must meet: max_i |a_i - a_fp64,i| / (|a_fp64,i| + a_rms), against the library's
+# own FP64 evaluation of the same state (the tests pin that one to the oracle)
+BOUND = {"fp32": float("inf"), "fp32c": float("inf"), "fp32ds": 1e-6, "fp64": 1e-12}
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
+
+
+def size_class(maxn: int) -> int:
+    return 0 if maxn < 2048 else 1 if maxn < 32768 else 2
+
+
+def _scale(a_all: np.ndarray, rows) -> np.ndarray:
+    """|a_i| + a_rms for the sampled rows (a_rms over the whole batch)."""
+    norm = np.linalg.norm(a_all, axis=1)
+    return np.maximum(norm[rows] + np.sqrt(np.mean(norm ** 2)), 1e-300)
+
+
+def sweep(batch, prec: str, shapes=None, tiles=None, bpcs=None, reps: int = 3, sample: int = 4096,
+          device: int = 0) -> List[Dict]:
+    """Time and check every shape for one workload; returns one dict per shape."""
+    import torch
+    shapes = shapes or SHAPES
+    tiles = tiles or TILES
+    bpcs = bpcs or BLOCKS_PER_CU
+    nclass = size_class(int(np.diff(batch.offsets).max()))
+    ref = nbody.Simulation(batch, "fp64", device)
+    ref.accel()
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(batch.n, size=min(sample, batch.n), replace=False))
+    a_all = ref.acc.cpu().numpy()
+    aref = a_all[rows]
+    scale = _scale(a_all, rows)
+    ref.close()
+    sim = nbody.Simulation(batch, prec, device)
+    out = []
+    for (k, w) in shapes:
+        for t in tiles:
+            for bpc in bpcs:
+                nbody.nbody_set_tile(sim.ctx, prec, nclass, k, w, t, bpc)
+                sim.accel()
+                torch.cuda.synchronize()
+                nbody.nbody_timing_read(sim.ctx)
+                nbody.nbody_timing_enable(sim.ctx, True)
+                for _ in range(reps):
+                    sim.accel()
+                torch.cuda.synchronize()
+                nbody.nbody_timing_enable(sim.ctx, False)
+                ms, n = nbody.nbody_timing_read(sim.ctx)
+                a = sim.acc.cpu().numpy()[rows]
+                err = float((np.linalg.norm(a - aref, axis=1) / scale).max())
+                out.append(dict(k=k, w=w, tile=t, bpc=bpc, ms=ms / max(n, 1), err=err,
+                                ok=err <= BOUND[prec], nclass=nclass))
+    sim.close()
+    return out
+
+
+def best(results: List[Dict]) -> Optional[Dict]:
+    ok = [r for r in results if r["ok"]]
+    return min(ok, key=lambda r: r["ms"]) if ok else None
+
+
+def load_cache(path: str = CACHE) -> Dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save(prec: str, nclass: int, cfg: Dict, arch: str = "gfx950", path: str = CACHE, note: str = "") -> None:
+    data = load_cache(path)
+    key = "%s/%s/%d" % (arch, FAMILY[prec], nclass)
+    data[key] = dict(k=cfg["k"], w=cfg["w"], tile=cfg["tile"], bpc=cfg["bpc"], ms=cfg["ms"], err=cfg["err"],
+                     note=note, when=time.strftime("%Y-%m-%d"))
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def apply(ctx, arch: str = "gfx950", path: str = CACHE, fixed_tile: Optional[Dict[str, tuple]] = None) -> int:
+    """Apply cached shapes to a context; returns how many were applied.  ``fixed_tile`` maps a
+    family to (tile, waves_per_group) to force the same FP32 fold pattern in every class (so that
+    a cluster's result does not depend on the batch it runs in)."""
+    data = load_cache(path)
+    n = 0
+    for key, cfg in data.items():
+        a, fam, ncl = key.split("/")
+        if a != arch:
+            continue
+        prec = {"f32": "fp32c", "ds": "fp32ds", "f64": "fp64"}[fam]
+        tile, w = cfg["tile"], cfg["w"]
+        k = cfg["k"]
+        if fixed_tile and fam in fixed_tile:
+            tile, w = fixed_tile[fam]
+            if (k, w) not in SHAPES:
+                k = 1
+        nbody.nbody_set_tile(ctx, prec, int(ncl), k, w, tile, cfg["bpc"])
+        n += 1
+    return n

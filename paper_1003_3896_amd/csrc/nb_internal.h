@@ -71,8 +71,10 @@ struct Args {
   int prec;  // NB_FP32 .. NB_FP64
 };
 
+// Pair-kernel launch shape: K i-particles per lane, W waves sharing an i-group, T j-records per
+// LDS tile, bpc persistent blocks per CU.
 struct TileCfg {
-  int k, tile, bpc;
+  int k, w, tile, bpc;
 };
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
@@ -83,5 +85,12 @@ hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, boo
 hipError_t launch_energy(const Args& a, hipStream_t s);
 
 bool tile_supported(int family, const TileCfg& t);
+// i-particles of one pair work item for a shape
+inline int item_tile(const TileCfg& t) { return 64 * t.k * (4 / t.w); }
+
+typedef void (*PairFn)(Args, int);
+PairFn pair_kernel_f32(const TileCfg& t, bool fold, bool mask, bool pot);
+PairFn pair_kernel_ds(const TileCfg& t, bool fold, bool mask, bool pot);
+PairFn pair_kernel_f64(const TileCfg& t, bool fold, bool mask, bool pot);
 
 }  // namespace nb

@@ -1,0 +1,379 @@
+// All-pairs softened gravity (Sect. 2, Eq. 5) for gfx950: kernel templates.
+//
+// Persistent ragged kernel.  The grid holds a few blocks per CU; each block repeatedly takes the
+// next work item (one i-tile of one cluster) from a device counter.  Items are ordered largest
+// cluster first, so long items start early and short ones fill the tail.
+//
+// Block = 4 wavefronts of 64 lanes.  The 4 waves form 4/W groups; the W waves of a group hold
+// the same K*64 i-particles (K per lane, in registers) and split every j-tile between them, so a
+// cluster of N particles keeps N/64*W waves busy (occupancy for the latency of the dependent
+// FP32 chain) without any extra global traffic.  The block streams the cluster's j-records
+// through LDS in tiles of T (coalesced 16/32-byte loads from HBM/L2); each wave reads its part of
+// the tile as LDS broadcasts.  At the end of an item the W partial sums of a group are combined in
+// LDS in a fixed order (deterministic).  The pair term runs on the VALU (v_rsq_f32, or v_rsq_f64
+// refined by one third-order Newton step); the sum is not a dense contraction, so no MFMA.
+//
+// FP32 families keep a wave's partial sum over its part of one tile (T/W terms) in FP32 and fold
+// it into FP64 after every tile; pure-FP32 mode keeps one FP32 sum.  The double-single family forms
+// each coordinate difference as (xj_hi - xi_hi) + (xj_lo - xi_lo): the hi difference is exact for
+// close pairs, so the difference carries FP32 relative accuracy however close the pair is.
+//
+// The results for a particle depend only on its own cluster's data and on (T, W): never on the
+// other clusters of the batch, on K, on the number of blocks, or on which block took which item.
+#pragma once
+#include "nb_device.h"
+
+namespace nb {
+
+template <int FAM, int T>
+struct PairLds;
+template <int T>
+struct PairLds<FAM_F32, T> {
+  float4 hi[T];
+  __device__ const float4& lo_at(int i) const { return hi[i]; }  // unused by the FP32 family
+};
+template <int T>
+struct PairLds<FAM_DS, T> {
+  float4 hi[T];
+  float4 lo[T];
+  __device__ const float4& lo_at(int i) const { return lo[i]; }
+};
+template <int T>
+struct PairLds<FAM_F64, T> {
+  double4 r[T];
+};
+
+// Epilogue of one particle: scale by G, add the galaxy field, store, optional kick.
+__device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
+                                                double ax, double ay, double az, bool round32, int kick) {
+  ax *= a.G;
+  ay *= a.G;
+  az *= a.G;
+  if (round32) {
+    ax = (float)ax;
+    ay = (float)ay;
+    az = (float)az;
+  }
+  if (c.flags & kFlagField) {
+    double ex, ey, ez;
+    galaxy_accel(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
+    ax += ex;
+    ay += ey;
+    az += ez;
+    if (round32) {
+      ax = (float)ax;
+      ay = (float)ay;
+      az = (float)az;
+    }
+  }
+  if (a.acc) {
+    a.acc[3 * gi] = ax;
+    a.acc[3 * gi + 1] = ay;
+    a.acc[3 * gi + 2] = az;
+  }
+  if (kick) {
+    const double kp = a.coef ? a.coef[3 * cluster + 2] : a.kick_post;
+    double* v = a.vel + 3 * gi;
+    if (round32) {
+      v[0] = fmaf((float)kp, (float)ax, (float)v[0]);
+      v[1] = fmaf((float)kp, (float)ay, (float)v[1]);
+      v[2] = fmaf((float)kp, (float)az, (float)v[2]);
+    } else {
+      v[0] = fma(kp, ax, v[0]);
+      v[1] = fma(kp, ay, v[1]);
+      v[2] = fma(kp, az, v[2]);
+    }
+  }
+}
+
+// Takes the next work item for the whole block; returns -1 when none is left.
+__device__ __forceinline__ int next_item(const Args& a, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = atomicAdd(a.item_counter, 1);
+  __syncthreads();
+  const int it = *s_item;
+  return it < a.nitems ? it : -1;
+}
+
+// Loads one j-tile into LDS (padding beyond the cluster with zero-mass records far away, whose
+// terms are exactly 0 and never NaN).
+template <int FAM, int T>
+__device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, long long base, int cnt) {
+  const int tid = threadIdx.x;
+  if (tid >= T) return;
+  if constexpr (FAM == FAM_F64) {
+    sh.r[tid] = tid < cnt ? a.rec64[base + tid] : make_double4(1e150, 1e150, 1e150, 0.0);
+  } else {
+    if (tid < cnt) {
+      sh.hi[tid] = a.rec_hi[base + tid];
+      if constexpr (FAM == FAM_DS) sh.lo[tid] = a.rec_lo[base + tid];
+    } else {
+      sh.hi[tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+      if constexpr (FAM == FAM_DS) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+}
+
+// Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
+// red: [4 waves][64*K lanes][4] doubles (ax, ay, az, pot).
+template <int K, int W, bool POT>
+__device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluster& c, int cluster, int ibase,
+                                                  const double (&Ax)[K], const double (&Ay)[K], const double (&Az)[K],
+                                                  const double (&Pt)[K], double* red, bool round32, int kick) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = wave % W;
+  if constexpr (W > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double* r = red + ((size_t)wave * 64 * K + k * 64 + lane) * 4;
+      r[0] = Ax[k];
+      r[1] = Ay[k];
+      r[2] = Az[k];
+      r[3] = POT ? Pt[k] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (sub != 0) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int li = ibase + k * 64;
+    double ax = Ax[k], ay = Ay[k], az = Az[k], pt = POT ? Pt[k] : 0.0;
+    if constexpr (W > 1) {
+#pragma unroll
+      for (int s = 1; s < W; ++s) {
+        const double* r = red + ((size_t)(wave + s) * 64 * K + k * 64 + lane) * 4;
+        ax += r[0];
+        ay += r[1];
+        az += r[2];
+        if (POT) pt += r[3];
+      }
+    }
+    if (li >= c.n) continue;
+    const long long gi = c.off + li;
+    finish_particle(a, c, cluster, gi, ax, ay, az, round32, kick);
+    if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP32 and double-single families
+
+// One j-record against the K i-particles of this lane:
+//   d = x_j - x_i (double-single: (hi_j - hi_i) + (lo_j - lo_i)),  r2 = |d|^2 + eps^2,
+//   s = m_j r2^{-3/2},  a += s d,  and with POT  pot += m_j r2^{-1/2} for j != i.
+template <bool DS, int K, bool MASK, bool POT>
+__device__ __forceinline__ void interact32(const float4 pj, const float4 pl, const float (&xi)[K], const float (&yi)[K],
+                                           const float (&zi)[K], const float (&xl)[K], const float (&yl)[K],
+                                           const float (&zl)[K], float e2, float (&ax)[K], float (&ay)[K],
+                                           float (&az)[K], float (&pt)[K], const int (&li)[K], int j) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float dx = pj.x - xi[k], dy = pj.y - yi[k], dz = pj.z - zi[k];
+    if constexpr (DS) {
+      dx += pl.x - xl[k];
+      dy += pl.y - yl[k];
+      dz += pl.z - zl[k];
+    }
+    float r2 = fmaf(dx, dx, e2);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float mi = pj.w * inv;
+    float s = mi * (inv * inv);
+    if (MASK) s = r2 > 0.0f ? s : 0.0f;
+    ax[k] = fmaf(dx, s, ax[k]);
+    ay[k] = fmaf(dy, s, ay[k]);
+    az[k] = fmaf(dz, s, az[k]);
+    if (POT) pt[k] += (j != li[k]) ? mi : 0.0f;
+  }
+}
+
+template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT>
+__global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
+  static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
+  constexpr bool DS = FAM == FAM_DS;
+  constexpr int TW = T / W;      // records per wave per tile
+  __shared__ PairLds<FAM, T> sh;
+  __shared__ double red[W > 1 ? 4 * 64 * K * 4 : 1];
+  __shared__ int s_item;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / W, sub = wave % W;
+  for (int it; (it = next_item(a, &s_item)) >= 0;) {
+    const PairItem item = a.items[it];
+    const DevCluster c = a.cl[item.cluster];
+    const int ibase = item.i0 + grp * 64 * K + lane;
+    float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K];
+    float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K];
+    double Ax[K], Ay[K], Az[K], Pt[K];
+    int li[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      li[k] = ibase + k * 64;
+      const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
+      const float4 p = a.rec_hi[gi];
+      xi[k] = p.x;
+      yi[k] = p.y;
+      zi[k] = p.z;
+      if constexpr (DS) {
+        const float4 q = a.rec_lo[gi];
+        xl[k] = q.x;
+        yl[k] = q.y;
+        zl[k] = q.z;
+      }
+      if constexpr (!DS) xl[k] = yl[k] = zl[k] = 0.0f;
+      ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = pt[k] = 0.0f;
+      Ax[k] = Ay[k] = Az[k] = Pt[k] = 0.0;
+    }
+    const float e2 = c.eps2f;
+    for (int j0 = 0; j0 < c.n; j0 += T) {
+      const int cnt = min(T, c.n - j0);
+      __syncthreads();
+      load_tile<FAM, T>(a, sh, c.off + j0, cnt);
+      __syncthreads();
+      const int u0 = sub * TW;
+      if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
+#pragma unroll 2
+        for (int u = u0; u < u0 + TW; u += 8) {
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+            interact32<DS, K, MASK, POT>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
+                                         (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li, j0 + u + v);
+        }
+      } else {
+        const int mine = min(TW, ((cnt - u0 + 7) & ~7));  // this wave's records, padded to 8
+        for (int u = u0; u < u0 + mine; u += 8) {
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+            interact32<DS, K, MASK, POT>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
+                                         (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li, j0 + u + v);
+        }
+      }
+      if (FOLD) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          Ax[k] += (double)ax[k] + (double)bx[k];
+          Ay[k] += (double)ay[k] + (double)by[k];
+          Az[k] += (double)az[k] + (double)bz[k];
+          ax[k] = ay[k] = az[k] = 0.0f;
+          bx[k] = by[k] = bz[k] = 0.0f;
+          if (POT) {
+            Pt[k] += (double)pt[k];
+            pt[k] = 0.0f;
+          }
+        }
+      }
+    }
+    if (!FOLD) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        Ax[k] = ax[k] + bx[k];
+        Ay[k] = ay[k] + by[k];
+        Az[k] = az[k] + bz[k];
+        Pt[k] = pt[k];
+      }
+    }
+    reduce_and_finish<K, W, POT>(a, c, item.cluster, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP64 family
+template <int K, int W, int T, bool MASK, bool POT>
+__global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
+  static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
+  constexpr int TW = T / W;
+  __shared__ PairLds<FAM_F64, T> sh;
+  __shared__ double red[W > 1 ? 4 * 64 * K * 4 : 1];
+  __shared__ int s_item;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / W, sub = wave % W;
+  for (int it; (it = next_item(a, &s_item)) >= 0;) {
+    const PairItem item = a.items[it];
+    const DevCluster c = a.cl[item.cluster];
+    const int ibase = item.i0 + grp * 64 * K + lane;
+    double xi[K], yi[K], zi[K], ax[K], ay[K], az[K], pt[K];
+    int li[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      li[k] = ibase + k * 64;
+      const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
+      const double4 p = a.rec64[gi];
+      xi[k] = p.x;
+      yi[k] = p.y;
+      zi[k] = p.z;
+      ax[k] = ay[k] = az[k] = pt[k] = 0.0;
+    }
+    const double e2 = c.eps2;
+    for (int j0 = 0; j0 < c.n; j0 += T) {
+      const int cnt = min(T, c.n - j0);
+      __syncthreads();
+      load_tile<FAM_F64, T>(a, sh, c.off + j0, cnt);
+      __syncthreads();
+      const int u0 = sub * TW;
+      const int mine = min(TW, ((cnt - u0 + 7) & ~7));
+      for (int u = u0; u < u0 + mine; u += 8) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const double4 pj = sh.r[u + v];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double dx = pj.x - xi[k], dy = pj.y - yi[k], dz = pj.z - zi[k];
+            double r2 = fma(dx, dx, e2);
+            r2 = fma(dy, dy, r2);
+            r2 = fma(dz, dz, r2);
+            const double inv = rsqrt_f64(r2);
+            const double mi = pj.w * inv;
+            double s = mi * (inv * inv);
+            if (MASK) s = r2 > 0.0 ? s : 0.0;
+            ax[k] = fma(dx, s, ax[k]);
+            ay[k] = fma(dy, s, ay[k]);
+            az[k] = fma(dz, s, az[k]);
+            if (POT) pt[k] += (j0 + u + v != li[k]) ? mi : 0.0;
+          }
+        }
+      }
+    }
+    reduce_and_finish<K, W, POT>(a, c, item.cluster, ibase, ax, ay, az, pt, red, false, kick);
+  }
+}
+
+// Kernel for one shape and flag set of a family (nullptr when not compiled in).
+template <int FAM, int K, int W, int T>
+PairFn pair_flags(bool fold, bool mask, bool pot) {
+  if constexpr (FAM == FAM_F64) {
+    if (mask) return pot ? k_pair64<K, W, T, true, true> : k_pair64<K, W, T, true, false>;
+    return pot ? k_pair64<K, W, T, false, true> : k_pair64<K, W, T, false, false>;
+  } else if constexpr (FAM == FAM_DS) {
+    if (mask) return pot ? k_pair32<FAM, K, W, T, true, true, true> : k_pair32<FAM, K, W, T, true, true, false>;
+    return pot ? k_pair32<FAM, K, W, T, true, false, true> : k_pair32<FAM, K, W, T, true, false, false>;
+  } else {
+    if (fold) {
+      if (mask) return pot ? k_pair32<FAM, K, W, T, true, true, true> : k_pair32<FAM, K, W, T, true, true, false>;
+      return pot ? k_pair32<FAM, K, W, T, true, false, true> : k_pair32<FAM, K, W, T, true, false, false>;
+    }
+    if (mask) return pot ? k_pair32<FAM, K, W, T, false, true, true> : k_pair32<FAM, K, W, T, false, true, false>;
+    return pot ? k_pair32<FAM, K, W, T, false, false, true> : k_pair32<FAM, K, W, T, false, false, false>;
+  }
+}
+
+// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)}, T in {128, 256}.
+template <int FAM>
+PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
+#define NB_SHAPE(KK, WW, TT) \
+  if (t.k == KK && t.w == WW && t.tile == TT) return pair_flags<FAM, KK, WW, TT>(fold, mask, pot);
+  NB_SHAPE(1, 1, 128)
+  NB_SHAPE(1, 1, 256)
+  NB_SHAPE(1, 2, 128)
+  NB_SHAPE(1, 2, 256)
+  NB_SHAPE(1, 4, 128)
+  NB_SHAPE(1, 4, 256)
+  NB_SHAPE(2, 2, 128)
+  NB_SHAPE(2, 2, 256)
+  NB_SHAPE(2, 4, 128)
+  NB_SHAPE(2, 4, 256)
+#undef NB_SHAPE
+  return nullptr;
+}
+
+}  // namespace nb

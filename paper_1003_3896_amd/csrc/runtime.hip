@@ -162,7 +162,7 @@ Layout make_layout(int B, long long ntot, int nchunks) {
   L.chunks = o;
   o = align_up(o + sizeof(Chunk) * nchunks);
   L.items = o;
-  o = align_up(o + sizeof(PairItem) * nchunks);  // K = 1 has as many items as there are chunks
+  o = align_up(o + sizeof(PairItem) * 4 * nchunks);  // the smallest item tile is 64 particles
   L.coef = o;
   o = align_up(o + sizeof(double) * 3 * B);
   L.counters = o;  // [B] chunk counters + 1 item counter
@@ -219,12 +219,12 @@ int build_plan(const nbody_system* sys, Plan& p) {
 }
 
 // Pair work items for i-tiles of kBlock*K particles, largest clusters first (ties by index).
-void make_items(const Plan& p, int K, std::vector<PairItem>& items) {
+void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::vector<int> order(p.B);
   for (int b = 0; b < p.B; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].n > p.cl[y].n; });
   items.clear();
-  const int tile = kBlock * K;
+  const int tile = item_tile(t);
   for (int b : order)
     for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) items.push_back(PairItem{b, i0});
 }
@@ -273,7 +273,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   const int fam = family_of(sys->prec);
   const TileCfg t = ctx->tiles[fam][size_class(p.maxn)];
   std::vector<PairItem> items;
-  make_items(p, t.k, items);
+  make_items(p, t, items);
   // host blob: [clusters | chunks | items | coef | counters]
   const Layout& L = p.L;
   std::vector<unsigned char>& blob = ctx->blob;
@@ -403,7 +403,8 @@ int check_state(const Plan& p, const void* pos, const void* vel, const void* mas
 
 void default_tiles(nbody_ctx* ctx) {
   for (int f = 0; f < 3; ++f)
-    for (int c = 0; c < 3; ++c) ctx->tiles[f][c] = TileCfg{1, f == FAM_F32 ? 256 : 128, 4};
+    for (int c = 0; c < 3; ++c)
+      ctx->tiles[f][c] = f == FAM_F32 ? TileCfg{1, 4, 128, 4} : f == FAM_DS ? TileCfg{2, 4, 128, 8} : TileCfg{2, 4, 256, 8};
 }
 
 int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass, double* acc,
@@ -597,10 +598,11 @@ int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
   if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
   if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
-  TileCfg t{tile.k, tile.tile, tile.blocks_per_cu};
+  TileCfg t{tile.k, tile.waves_per_group, tile.tile, tile.blocks_per_cu};
   const int fam = family_of(prec);
   if (!tile_supported(fam, t))
-    return fail(NB_ERR_ARG, "tile (k=%d, tile=%d, blocks_per_cu=%d) is not compiled in", t.k, t.tile, t.bpc);
+    return fail(NB_ERR_ARG, "tile (k=%d, w=%d, tile=%d, blocks_per_cu=%d) is not compiled in", t.k, t.w, t.tile,
+                t.bpc);
   ctx->tiles[fam][nclass] = t;
   return NB_OK;
 }
@@ -611,6 +613,7 @@ int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_til
   if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
   const TileCfg& t = ctx->tiles[family_of(prec)][nclass];
   tile->k = t.k;
+  tile->waves_per_group = t.w;
   tile->tile = t.tile;
   tile->blocks_per_cu = t.bpc;
   return NB_OK;

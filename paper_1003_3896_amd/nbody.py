@@ -52,7 +52,8 @@ class nbody_system(ctypes.Structure):
 
 
 class nbody_tile(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_int32), ("tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("k", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
 
 
 _lib = None
@@ -220,16 +221,16 @@ def nbody_energy(ctx, sys: System, pos, vel, mass, out, ws, ws_bytes: int, strea
                               int(ws_bytes), _stream(stream)))
 
 
-def nbody_set_tile(ctx, prec, nclass: int, k: int, tile: int, blocks_per_cu: int) -> None:
+def nbody_set_tile(ctx, prec, nclass: int, k: int, waves_per_group: int, tile: int, blocks_per_cu: int) -> None:
     prec = PREC[prec] if isinstance(prec, str) else prec
-    _check(lib().nbody_set_tile(ctx, int(prec), int(nclass), nbody_tile(k, tile, blocks_per_cu)))
+    _check(lib().nbody_set_tile(ctx, int(prec), int(nclass), nbody_tile(k, waves_per_group, tile, blocks_per_cu)))
 
 
 def nbody_get_tile(ctx, prec, nclass: int):
     prec = PREC[prec] if isinstance(prec, str) else prec
     t = nbody_tile()
     _check(lib().nbody_get_tile(ctx, int(prec), int(nclass), ctypes.byref(t)))
-    return (t.k, t.tile, t.blocks_per_cu)
+    return (t.k, t.waves_per_group, t.tile, t.blocks_per_cu)
 
 
 def nbody_timing_enable(ctx, enable: bool) -> None:
