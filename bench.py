@@ -18,6 +18,8 @@ Other workloads (--workload c1|c2|c4) run their own configurations.
 """
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import math
 import os
@@ -38,7 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--jobs", type=int, default=120, help="c5: jobs in the open-loop stream")
+    ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
+    ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
     ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
@@ -98,6 +103,40 @@ def time_steps(sim, integrator, dt, steps, warmup, torch):
     return t1 - t0, kms, nlaunch
 
 
+def per_cluster_baseline(batch, integrator, dt, steps, torch):
+    """The same kernels launched cluster by cluster (one single-cluster system per call, one stream,
+    no graphs): what the batched persistent launch is compared against."""
+    from paper_1003_3896_amd import nbody
+    sim = nbody.Simulation(batch, "fp32ds")
+    ctx = sim.ctx
+    nbody.nbody_use_graphs(ctx, False)
+    sizes = np.diff(batch.offsets)
+    big = int(sizes.max())
+    one = nbody.System([0, big], [batch.eps[0]], None, batch.G, batch.galaxy, "fp32ds")
+    wsb = nbody.nbody_workspace_bytes(ctx, one)
+    ws = torch.empty(wsb + 256, dtype=torch.uint8, device="cuda")
+    wsa = (ws.data_ptr() + 255) & ~255
+    systems = [nbody.System([0, int(n)], [batch.eps[c]], None if batch.field is None else [batch.field[c]],
+                            batch.G, batch.galaxy, "fp32ds") for c, n in enumerate(sizes)]
+    fn = nbody.nbody_step_leapfrog if integrator == "leapfrog" else nbody.nbody_step_sym6
+    P, V, M, A = (sim.pos.data_ptr(), sim.vel.data_ptr(), sim.mass.data_ptr(), sim.acc.data_ptr())
+    sim.accel()
+
+    def run(nst):
+        for c, sysc in enumerate(systems):
+            o = int(batch.offsets[c])
+            fn(ctx, sysc, P + 24 * o, V + 24 * o, M + 8 * o, A + 24 * o, dt, nst, wsa, wsb)
+
+    run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.close()
+    return el
+
+
 def cpu_baseline(batch, pos_all, target_s, a_gpu):
     """Time the FP64 oracle on a block of rows of the first cluster against all of its sources, at
     the positions the GPU run ended with (so the same rows double as a parity sample)."""
@@ -130,13 +169,85 @@ def cpu_baseline(batch, pos_all, target_s, a_gpu):
     }, {"rows": rows, "max": float(err.max()), "median": float(np.median(err))}
 
 
+def serve_requests(jobs):
+    from paper_1003_3896_amd.serve import Request
+    reqs = []
+    for j in jobs:
+        p, v, m = j.initial_state()
+        reqs.append(Request(j.jid, p, v, m, j.steps, j.integrator, j.dt, j.eps, j.field, j.arrival))
+    return reqs
+
+
+def bench_c5(args):
+    """Served stream: closed-loop saturation throughput first, then Poisson arrivals at the given
+    fraction of it; latency = arrival -> final state and energy on the host."""
+    import torch
+    from paper_1003_3896_amd import inputs
+    from paper_1003_3896_amd.serve import HipExecutor, Server, latency_stats
+    torch.cuda.set_device(0)
+    cap, maxb = 1 << 20, 256
+    ex = HipExecutor(cap, maxb, "fp32ds")
+    # saturation: all jobs present at t = 0; throughput over the rounds with a backlog
+    sat = serve_requests(inputs.c5_jobs(args.sat_jobs, 0.0, seed=5006))
+    for r in sat:
+        r.arrival = 0.0
+    srv = Server(ex, energy=False)
+    t0 = time.perf_counter()
+    res = srv.run(sat)
+    el = time.perf_counter() - t0
+    work = sum(r.interactions() for r in sat if res[r.jid].status == "done")
+    xsat = work / el
+    print("c5: saturation %.3e int/s over %d jobs in %.1f s" % (xsat, len(sat), el), file=sys.stderr, flush=True)
+    mean_work = 5.16e8 * 505 * 4  # E[N^2] E[steps] E[evals/step] of the job distribution
+    rate = args.load * xsat / mean_work
+    jobs = inputs.c5_jobs(args.jobs, rate)
+    reqs = serve_requests(jobs)
+    srv = Server(ex, energy=True)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    el = time.perf_counter() - t0
+    done = [r for r in reqs if res[r.jid].status == "done"]
+    work = sum(r.interactions() for r in done)
+    warm = max(1, args.jobs // 20)
+    lat = latency_stats(res, skip=warm)
+    dE = [res[r.jid].rel_energy_error for r in done]
+    ex.close()
+    return {
+        "metric": METRIC,
+        "value": round(work / el / 1e9, 3),
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": len(done),
+        "warmup": warm,
+        "ms_per_step": round(el / max(len(done), 1) * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Plummer jobs, Poisson arrivals)",
+        "config": {"workload": "served stream: N log-uniform [1024,65536], steps U[10,1000], leapfrog/sym6 "
+                               "50/50, galaxy field on half, eps=1e-3, dt=2^-11, fp32ds",
+                   "jobs": args.jobs, "offered_load": args.load, "arrival_rate_per_s": round(rate, 4),
+                   "arena_particles": cap, "max_clusters": maxb},
+        "latency_s": {"p50": round(lat["p50"], 4), "p99": round(lat["p99"], 4), "mean": round(lat.get("mean", 0), 4),
+                      "jobs_counted": lat["n"]},
+        "saturation_G_interactions_per_s": round(xsat / 1e9, 3),
+        "rounds": srv.rounds,
+        "jobs_done": len(done),
+        "jobs_failed": sum(1 for r in reqs if res[r.jid].status != "done"),
+        "max_rel_energy_error": float(np.nanmax(dE)) if dE else None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU split is not part of this build "
               "(asked for --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if args.workload == "c5":
+        print(json.dumps(bench_c5(args)), flush=True)
+        return
     import torch
     from paper_1003_3896_amd import inputs, nbody
 
@@ -220,6 +331,12 @@ def main():
     }
     if modes:
         result["modes"] = modes
+    if args.workload == "c4":
+        bsteps = max(1, min(args.steps, 3))
+        el = per_cluster_baseline(batch, integrator, dt, bsteps, torch)
+        per = inter_per_eval * evals_per_step * bsteps / el / 1e9
+        result["per_cluster_launches"] = {"G_interactions_per_s": round(per, 3), "steps": bsteps,
+                                          "batched_over_per_cluster": round(value / per, 2)}
     if not args.no_cpu_baseline:
         cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
         result["cpu_baseline"] = cb

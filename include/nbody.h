@@ -134,6 +134,11 @@ int nbody_step_leapfrog(nbody_ctx* ctx, const nbody_system* sys, double* pos, do
 int nbody_step_sym6(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
                     double* acc, double dt, int32_t nsteps, void* ws, size_t ws_bytes, void* stream);
 
+/* The 7 drift and 8 kick weights of the 6th-order composition above (drift7[k] = w of stage k,
+ * kick8[0] = w3/2, kick8[k] = (w_{k-1} + w_k)/2, kick8[7] = w3/2), as nbody_step_sym6 uses them;
+ * host arrays.  Lets a caller drive the same integrator one stage at a time with nbody_substep. */
+int nbody_sym6_coefficients(double* drift7, double* kick8);
+
 /* Diagnostics of Sect. 5.1 per cluster, written to the DEVICE array out[B][16] (float64):
  *   0 K = 1/2 sum m |v|^2     1 W = 1/2 sum m_i pot_i     2 Uext = sum m Phi_ext (field clusters)
  *   3 E = K + W + Uext         4..6 P = sum m v             7..9 L = sum m x cross v
@@ -166,6 +171,13 @@ typedef struct {
 } nbody_tile;
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);
+
+/* Step graphs (enable = 1, the default): nbody_step_leapfrog / nbody_step_sym6 calls with
+ * nsteps >= 2 capture the kernels of one step into a HIP graph (once per argument set; a change of
+ * any pointer, dt, system layout or launch shape recaptures) and replay it nsteps times on a
+ * context-owned stream ordered after, and before, the caller's stream.  Results are bitwise those of
+ * the direct launches.  Disabled automatically while per-kernel timing is on. */
+int nbody_use_graphs(nbody_ctx* ctx, int enable);
 
 /* Per-kernel timing with HIP events recorded on the call's stream around every pair-kernel
  * launch (enable = 1) or off (0, the default).  nbody_timing_read returns the summed duration

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -85,9 +86,21 @@ int family_of(int prec) { return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ?
 
 }  // namespace
 
+// One captured integrator step (all stages of one leapfrog or sym6 step) and the kernel-argument
+// key it was captured with; replayed nsteps times.
+struct StepGraph {
+  std::vector<unsigned char> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct nbody_ctx {
   int device = 0;
   int cus = 256;
+  bool graphs = true;
+  hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  StepGraph sg;
   TileCfg tiles[3][3];
   Slot slots[4];
   int next_slot = 0;
@@ -404,7 +417,83 @@ int check_state(const Plan& p, const void* pos, const void* vel, const void* mas
 void default_tiles(nbody_ctx* ctx) {
   for (int f = 0; f < 3; ++f)
     for (int c = 0; c < 3; ++c)
-      ctx->tiles[f][c] = f == FAM_F32 ? TileCfg{1, 4, 128, 4} : f == FAM_DS ? TileCfg{2, 4, 128, 8} : TileCfg{2, 4, 256, 8};
+      ctx->tiles[f][c] = c == 0 ? TileCfg{1, 4, 128, 8}
+                       : f == FAM_F32 ? TileCfg{1, 4, 128, 4}
+                       : f == FAM_DS  ? TileCfg{2, 4, 128, 8}
+                                      : TileCfg{2, 4, 256, 8};
+}
+
+// Key of a captured step: every kernel argument except the per-stage coefficients, plus dt (via
+// the coefficients of the first stage), the launch shape and the kernel choice.
+template <class F>
+std::vector<unsigned char> graph_key(const Prepared& P, bool mask, int stages, F& set_stage) {
+  std::vector<unsigned char> key;
+  auto put = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    key.insert(key.end(), c, c + n);
+  };
+  for (int k = 0; k < stages; ++k) {
+    Args a;
+    memset(&a, 0, sizeof a);
+    a = P.a;
+    set_stage(k);
+    a.kick_pre = P.a.kick_pre;
+    a.drift = P.a.drift;
+    a.kick_post = P.a.kick_post;
+    put(&a.kick_pre, sizeof(double) * 3);
+    if (k == 0) {
+      put(&a.cl, offsetof(Args, kick_pre));
+      put(&a.G, sizeof(double));
+      put(&a.gal, sizeof(Galaxy));
+      put(&a.prec, sizeof(int));
+    }
+  }
+  put(&P.tile, sizeof P.tile);
+  put(&P.grid, sizeof P.grid);
+  put(&P.centred, sizeof P.centred);
+  put(&mask, sizeof mask);
+  put(&stages, sizeof stages);
+  return key;
+}
+
+// Launch nsteps replays of the captured step graph on the context's stream, ordered after the
+// caller's stream and before anything the caller issues next on it.
+template <class F>
+int replay_step_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t nsteps, hipStream_t s) {
+  int rc;
+  if (!ctx->gstream) {
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+  }
+  std::vector<unsigned char> key = graph_key(P, ctx->plan.anymask, stages, set_stage);
+  StepGraph& g = ctx->sg;
+  if (!g.exec || g.key != key) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.key.clear();
+    HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < stages; ++k) {
+      set_stage(k);
+      if ((rc = evaluate(ctx, P, true, false, k == stages - 1, ctx->gstream))) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(ctx->gstream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        return rc;
+      }
+    }
+    HIP_TRY(hipStreamEndCapture(ctx->gstream, &g.graph));
+    HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    g.key = key;
+  }
+  HIP_TRY(hipEventRecord(ctx->ev_in, s));
+  HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+  for (int32_t step = 0; step < nsteps; ++step) HIP_TRY(hipGraphLaunch(g.exec, ctx->gstream));
+  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->gstream));
+  HIP_TRY(hipStreamWaitEvent(s, ctx->ev_out, 0));
+  return NB_OK;
 }
 
 int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass, double* acc,
@@ -427,17 +516,21 @@ int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel,
   P.a.acc = acc;
   P.a.mass = mass;
   P.a.pot = nullptr;
-  for (int32_t step = 0; step < nsteps; ++step) {
-    const int stages = sym6 ? 7 : 1;
-    for (int k = 0; k < stages; ++k) {
-      P.a.kick_pre = (sym6 ? kSym6.k[k] : 0.5) * dt;
-      P.a.drift = (sym6 ? kSym6.d[k] : 1.0) * dt;
-      const bool last = k == stages - 1;
-      P.a.kick_post = last ? (sym6 ? kSym6.k[7] : 0.5) * dt : 0.0;
-      if ((rc = evaluate(ctx, P, true, false, last, s))) return rc;
-    }
+  const int stages = sym6 ? 7 : 1;
+  auto set_stage = [&](int k) {
+    P.a.kick_pre = (sym6 ? kSym6.k[k] : 0.5) * dt;
+    P.a.drift = (sym6 ? kSym6.d[k] : 1.0) * dt;
+    P.a.kick_post = (k == stages - 1) ? (sym6 ? kSym6.k[7] : 0.5) * dt : 0.0;
+  };
+  if (!ctx->graphs || ctx->timing || nsteps < 2) {
+    for (int32_t step = 0; step < nsteps; ++step)
+      for (int k = 0; k < stages; ++k) {
+        set_stage(k);
+        if ((rc = evaluate(ctx, P, true, false, k == stages - 1, s))) return rc;
+      }
+    return NB_OK;
   }
-  return NB_OK;
+  return replay_step_graph(ctx, P, stages, set_stage, nsteps, s);
 }
 
 }  // namespace
@@ -477,6 +570,12 @@ void nbody_destroy(nbody_ctx* ctx) {
     (void)hipEventDestroy(pr.second);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
+  if (ctx->sg.exec) (void)hipGraphExecDestroy(ctx->sg.exec);
+  if (ctx->sg.graph) (void)hipGraphDestroy(ctx->sg.graph);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
   delete ctx;
 }
 
@@ -616,6 +715,19 @@ int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_til
   tile->waves_per_group = t.w;
   tile->tile = t.tile;
   tile->blocks_per_cu = t.bpc;
+  return NB_OK;
+}
+
+int nbody_sym6_coefficients(double* drift7, double* kick8) {
+  if (!drift7 || !kick8) return fail(NB_ERR_ARG, "NULL argument");
+  for (int i = 0; i < 7; ++i) drift7[i] = kSym6.d[i];
+  for (int i = 0; i < 8; ++i) kick8[i] = kSym6.k[i];
+  return NB_OK;
+}
+
+int nbody_use_graphs(nbody_ctx* ctx, int enable) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  ctx->graphs = enable != 0;
   return NB_OK;
 }
 

@@ -23,7 +23,8 @@ PREC = {"fp32": NB_FP32, "fp32c": NB_FP32C, "fp32ds": NB_FP32DS, "fp64": NB_FP64
 EXPORTS = (
     "nbody_create", "nbody_destroy", "nbody_workspace_bytes", "nbody_accel", "nbody_substep",
     "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_last_error", "nbody_set_tile",
-    "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions",
+    "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions", "nbody_use_graphs",
+    "nbody_sym6_coefficients",
 )
 
 ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M", "_", "nonfinite")
@@ -60,9 +61,13 @@ _lib = None
 
 
 def lib():
-    """Load libnbody.so (raises if it has not been built)."""
+    """Load libnbody.so (raises if it has not been built).
+
+    PyTorch is imported first so that the library binds to the HIP runtime PyTorch already loaded
+    (both carry the soname libamdhip64.so.7): one process must not run two HIP runtimes."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads PyTorch's HIP runtime before ours resolves it)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libnbody.so is not built (%s); run __graft_entry__.build() or "
                                "python -m paper_1003_3896_amd.build" % LIB_PATH)
@@ -83,11 +88,14 @@ def lib():
         L.nbody_set_tile.argtypes = [P, I32, I32, nbody_tile]
         L.nbody_get_tile.argtypes = [P, I32, I32, ctypes.POINTER(nbody_tile)]
         L.nbody_timing_enable.argtypes = [P, ctypes.c_int]
+        L.nbody_use_graphs.argtypes = [P, ctypes.c_int]
+        L.nbody_sym6_coefficients.argtypes = [P, P]
         L.nbody_timing_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
         L.nbody_interactions.argtypes = [SYS]
         L.nbody_interactions.restype = I64
         for name in ("nbody_create", "nbody_accel", "nbody_substep", "nbody_step_leapfrog", "nbody_step_sym6",
-                     "nbody_energy", "nbody_set_tile", "nbody_get_tile", "nbody_timing_enable",
+                     "nbody_energy", "nbody_set_tile", "nbody_get_tile", "nbody_timing_enable", "nbody_use_graphs",
+                     "nbody_sym6_coefficients",
                      "nbody_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -231,6 +239,18 @@ def nbody_get_tile(ctx, prec, nclass: int):
     t = nbody_tile()
     _check(lib().nbody_get_tile(ctx, int(prec), int(nclass), ctypes.byref(t)))
     return (t.k, t.waves_per_group, t.tile, t.blocks_per_cu)
+
+
+def nbody_sym6_coefficients():
+    """(drift weights [7], kick weights [8]) of the 6th-order composition, from the library."""
+    d = np.zeros(7)
+    k = np.zeros(8)
+    _check(lib().nbody_sym6_coefficients(d.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p)))
+    return d, k
+
+
+def nbody_use_graphs(ctx, enable: bool) -> None:
+    _check(lib().nbody_use_graphs(ctx, 1 if enable else 0))
 
 
 def nbody_timing_enable(ctx, enable: bool) -> None:

@@ -1,0 +1,321 @@
+"""Continuous-batching request loop for N-body integration jobs.
+
+Jobs (one isolated cluster each: initial state, integrator, number of steps, softening, field
+flag) arrive over time.  The server keeps every admitted job's state on the device in one
+particle arena, concatenated in admission order, and advances ALL active jobs together: each
+round is one ``nbody_substep`` call over the ragged batch of active jobs, every job at its own
+integrator stage (its own kick/drift coefficients).  A job's first round is an evaluation-only
+substep (all coefficients 0) that produces its first acceleration; after that a leapfrog step is
+one substep (dt/2, dt, dt/2) and a 6th-order step is seven (the composition's merged kicks and
+drifts, taken from the library).  Jobs that arrive while others run are admitted as soon as arena
+space and cluster slots allow (admission by bytes of device memory), so their work overlaps on
+the device with the jobs already running; finished jobs are retired, their energy evaluated, and
+the arena compacted.
+
+Because each cluster's arithmetic depends only on its own data and on the pair kernel's fold
+pattern (pinned here to one tile shape for every cluster size), a job's result is bitwise the same
+whether it ran alone or in a mix.
+
+The device work goes through an executor; ``HipExecutor`` is the GPU one.  Tests drive the same
+control logic with a CPU stand-in.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import nbody
+
+STATE_BYTES_PER_PARTICLE = 80  # pos 24 + vel 24 + acc 24 + mass 8 (float64)
+
+
+@dataclass
+class Request:
+    """One integration job.  ``pos``/``vel``/``mass`` are the host initial state."""
+    jid: int
+    pos: np.ndarray
+    vel: np.ndarray
+    mass: np.ndarray
+    steps: int
+    integrator: str = "leapfrog"  # or "sym6"
+    dt: float = 2.0 ** -11
+    eps: float = 1e-3
+    field: bool = False
+    arrival: float = 0.0          # seconds after the start of the run
+
+    @property
+    def n(self) -> int:
+        return int(self.mass.shape[0])
+
+    def evals(self) -> int:
+        return self.steps * (1 if self.integrator == "leapfrog" else 7)
+
+    def interactions(self) -> int:
+        return self.evals() * self.n * self.n
+
+
+@dataclass
+class Result:
+    jid: int
+    status: str                   # "done", "failed", "rejected", "cancelled"
+    latency: float = float("nan")
+    pos: Optional[np.ndarray] = None
+    vel: Optional[np.ndarray] = None
+    energy0: Optional[np.ndarray] = None
+    energy1: Optional[np.ndarray] = None
+    reason: str = ""
+
+    @property
+    def rel_energy_error(self) -> float:
+        if self.energy0 is None or self.energy1 is None:
+            return float("nan")
+        return abs(self.energy1[3] - self.energy0[3]) / abs(self.energy0[3])
+
+
+@dataclass
+class _Active:
+    req: Request
+    offset: int
+    schedule: List[tuple]         # remaining (kick_pre, drift, kick_post) rounds
+    energy0: Optional[np.ndarray] = None
+    admitted_at: float = 0.0
+
+
+def stage_schedule(integrator: str, dt: float, steps: int, sym6: Optional[tuple] = None) -> List[tuple]:
+    """Coefficient triples of every round of a job: one evaluation-only round, then the steps."""
+    rounds = [(0.0, 0.0, 0.0)]
+    if integrator == "leapfrog":
+        rounds += [(0.5 * dt, 1.0 * dt, 0.5 * dt)] * steps
+    elif integrator == "sym6":
+        d, k = sym6 if sym6 is not None else nbody.nbody_sym6_coefficients()
+        one = [(k[s] * dt, d[s] * dt, (k[7] * dt) if s == 6 else 0.0) for s in range(7)]
+        rounds += one * steps
+    else:
+        raise ValueError("unknown integrator %r" % integrator)
+    return rounds
+
+
+class HipExecutor:
+    """Device side of the server: a particle arena, its workspace and the library context."""
+
+    def __init__(self, capacity: int, max_clusters: int, prec: str = "fp32ds", device: int = 0,
+                 energy_prec: str = "fp64", tile=(1, 4, 128, 8), G: float = 1.0, galaxy=None):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.capacity = int(capacity)
+        self.max_clusters = int(max_clusters)
+        self.prec = prec
+        self.energy_prec = energy_prec
+        self.G = G
+        self.galaxy = tuple(galaxy) if galaxy is not None else nbody.System([0, 1], [0.0]).galaxy
+        self.ctx = nbody.nbody_create(device)
+        # one launch shape for every size class: results independent of the batch composition
+        for p in {prec, energy_prec}:
+            for ncl in range(3):
+                nbody.nbody_set_tile(self.ctx, p, ncl, *tile)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.pos = torch.zeros(self.capacity, 3, **f64)
+        self.vel = torch.zeros(self.capacity, 3, **f64)
+        self.acc = torch.zeros(self.capacity, 3, **f64)
+        self.mass = torch.zeros(self.capacity, **f64)
+        self.eout = torch.zeros(self.max_clusters, 16, **f64)
+        self.ws_bytes = self._workspace_bound()
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        self.ws_addr = (self.ws.data_ptr() + 255) & ~255
+
+    def _workspace_bound(self) -> int:
+        """Workspace for the worst admissible batch: B-1 single particles and one big cluster
+        (the most chunks and work items for a given particle count and cluster count)."""
+        B = self.max_clusters
+        sizes = [1] * (B - 1) + [max(1, self.capacity - (B - 1))]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        return nbody.nbody_workspace_bytes(self.ctx, nbody.System(offs, np.ones(B), None, self.G, self.galaxy,
+                                                                  self.prec))
+
+    def footprint_bytes(self) -> int:
+        return STATE_BYTES_PER_PARTICLE * self.capacity + self.ws_bytes + 16 * 8 * self.max_clusters
+
+    def close(self):
+        if self.ctx:
+            self.torch.cuda.synchronize()
+            nbody.nbody_destroy(self.ctx)
+            self.ctx = None
+
+    def load(self, offset: int, req: Request) -> None:
+        t = self.torch
+        n = req.n
+        sl = slice(offset, offset + n)
+        self.pos[sl] = t.as_tensor(req.pos, dtype=t.float64).to(self.dev, non_blocking=False)
+        self.vel[sl] = t.as_tensor(req.vel, dtype=t.float64).to(self.dev, non_blocking=False)
+        self.mass[sl] = t.as_tensor(req.mass, dtype=t.float64).to(self.dev, non_blocking=False)
+        self.acc[sl].zero_()
+
+    def _system(self, sizes: Sequence[int], eps: Sequence[float], fld: Sequence[bool], prec: str):
+        offs = np.zeros(len(sizes) + 1, np.int64)
+        offs[1:] = np.cumsum(sizes)
+        return nbody.System(offs, np.asarray(eps, np.float64), np.asarray(fld, np.uint8), self.G, self.galaxy, prec)
+
+    def substep(self, sizes, eps, fld, kick_pre, drift, kick_post) -> None:
+        sys = self._system(sizes, eps, fld, self.prec)
+        nbody.nbody_substep(self.ctx, sys, self.pos, self.vel, self.mass, self.acc, kick_pre, drift, kick_post,
+                            self.ws_addr, self.ws_bytes)
+
+    def energy(self, offset: int, sizes, eps, fld) -> np.ndarray:
+        """Diagnostics of the consecutive jobs starting at ``offset`` (one row each)."""
+        sys = self._system(sizes, eps, fld, self.energy_prec)
+        o = int(offset)
+        B = len(sizes)
+        nbody.nbody_energy(self.ctx, sys, self.pos.data_ptr() + 24 * o, self.vel.data_ptr() + 24 * o,
+                           self.mass.data_ptr() + 8 * o, self.eout.data_ptr(), self.ws_addr, self.ws_bytes)
+        return self.eout[:B].cpu().numpy().copy()
+
+    def move(self, src: int, dst: int, n: int) -> None:
+        """Move n particles of state from src to dst < src (compaction)."""
+        if src == dst or n == 0:
+            return
+        for buf in (self.pos, self.vel, self.acc, self.mass):
+            buf[dst:dst + n] = buf[src:src + n].clone()
+
+    def read(self, offset: int, n: int):
+        sl = slice(offset, offset + n)
+        return self.pos[sl].cpu().numpy(), self.vel[sl].cpu().numpy()
+
+    def sync(self) -> None:
+        self.torch.cuda.synchronize()
+
+
+class Server:
+    """Admission, per-round batching, retirement and latency bookkeeping (device work in the
+    executor).  ``run(requests)`` replays arrival times against the wall clock."""
+
+    def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None):
+        self.ex = executor
+        self.energy = energy
+        self.clock = clock
+        self.sym6 = sym6 if sym6 is not None else nbody.nbody_sym6_coefficients()
+        self.active: List[_Active] = []
+        self.queue: List[Request] = []
+        self.results: Dict[int, Result] = {}
+        self.cancelled: set = set()
+        self.rounds = 0
+        self.interactions = 0
+
+    # -- admission -----------------------------------------------------------------------
+    def used(self) -> int:
+        return sum(a.req.n for a in self.active)
+
+    def fits(self, req: Request) -> bool:
+        return self.used() + req.n <= self.ex.capacity and len(self.active) < self.ex.max_clusters
+
+    def submit(self, req: Request) -> None:
+        if req.n < 1 or req.steps < 0 or not (req.dt == req.dt) or req.eps < 0:
+            self.results[req.jid] = Result(req.jid, "rejected", reason="invalid request")
+            return
+        if req.n > self.ex.capacity:
+            self.results[req.jid] = Result(req.jid, "rejected", reason="larger than the device arena")
+            return
+        self.queue.append(req)
+
+    def cancel(self, jid: int) -> None:
+        self.cancelled.add(jid)
+
+    def _admit(self, now: float) -> List[_Active]:
+        new = []
+        while self.queue and self.fits(self.queue[0]):
+            req = self.queue.pop(0)
+            if req.jid in self.cancelled:
+                self.results[req.jid] = Result(req.jid, "cancelled")
+                continue
+            off = self.used()
+            self.ex.load(off, req)
+            act = _Active(req, off, stage_schedule(req.integrator, req.dt, req.steps, self.sym6), admitted_at=now)
+            self.active.append(act)
+            new.append(act)
+        if new and self.energy:
+            e = self.ex.energy(new[0].offset, [a.req.n for a in new], [a.req.eps for a in new],
+                               [a.req.field for a in new])
+            for a, row in zip(new, e):
+                a.energy0 = row
+        return new
+
+    # -- one round -----------------------------------------------------------------------
+    def step_round(self) -> None:
+        acts = self.active
+        kp = np.array([a.schedule[0][0] for a in acts])
+        dr = np.array([a.schedule[0][1] for a in acts])
+        kq = np.array([a.schedule[0][2] for a in acts])
+        self.ex.substep([a.req.n for a in acts], [a.req.eps for a in acts], [a.req.field for a in acts], kp, dr, kq)
+        self.rounds += 1
+        for a in acts:
+            a.schedule.pop(0)
+            self.interactions += a.req.n * a.req.n
+
+    def _retire(self, now_fn) -> int:
+        done = [a for a in self.active if not a.schedule or a.req.jid in self.cancelled]
+        if not done:
+            return 0
+        for a in done:
+            if a.req.jid in self.cancelled:
+                self.results[a.req.jid] = Result(a.req.jid, "cancelled")
+                continue
+            e1 = None
+            if self.energy:
+                e1 = self.ex.energy(a.offset, [a.req.n], [a.req.eps], [a.req.field])[0]
+            pos, vel = self.ex.read(a.offset, a.req.n)
+            bad = (not np.all(np.isfinite(pos))) or (not np.all(np.isfinite(vel))) or (e1 is not None and e1[15] != 0)
+            self.results[a.req.jid] = Result(a.req.jid, "failed" if bad else "done", now_fn() - a.req.arrival, pos,
+                                             vel, a.energy0, e1, "non-finite state" if bad else "")
+        # compaction: keep survivors in admission order, contiguous from 0
+        keep = [a for a in self.active if a not in done]
+        off = 0
+        for a in keep:
+            self.ex.move(a.offset, off, a.req.n)
+            a.offset = off
+            off += a.req.n
+        self.active = keep
+        return len(done)
+
+    def run(self, requests: Sequence[Request], max_rounds: Optional[int] = None) -> Dict[int, Result]:
+        """Serve the requests; arrival times are seconds after the start of the call."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock()
+        now_fn = lambda: self.clock() - t0
+        i = 0
+        while i < len(pending) or self.queue or self.active:
+            now = now_fn()
+            while i < len(pending) and pending[i].arrival <= now:
+                self.submit(pending[i])
+                i += 1
+            self._admit(now)
+            if not self.active:
+                if i < len(pending) and not self.queue:
+                    wait = pending[i].arrival - now_fn()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                    continue
+                if self.queue and not self.active:
+                    # the head of the queue can never fit: reject it rather than stall
+                    r = self.queue.pop(0)
+                    self.results[r.jid] = Result(r.jid, "rejected", reason="does not fit")
+                continue
+            self.step_round()
+            if any(not a.schedule for a in self.active) or self.cancelled:
+                self.ex.sync()
+                self._retire(now_fn)
+            if max_rounds is not None and self.rounds >= max_rounds:
+                break
+        self.ex.sync()
+        return self.results
+
+
+def latency_stats(results: Dict[int, Result], skip: int = 0) -> dict:
+    lat = sorted(r.latency for j, r in results.items() if r.status == "done" and j >= skip)
+    if not lat:
+        return {"p50": float("nan"), "p99": float("nan"), "n": 0}
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "n": len(lat),
+            "mean": float(np.mean(lat))}
