@@ -64,10 +64,10 @@ def workload(name):
     return inputs.c4(), "fp32ds"
 
 
-def traffic_from_profile(prec):
+def traffic_from_profile(prec, tile=None):
     """HBM bytes per pair-kernel launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE calibrated against a plain copy), or None if the kernel source has changed since
-    the counters were taken or no summary exists for this mode."""
+    WRITE_SIZE calibrated against a plain copy), or None if the kernel source or the launch shape
+    has changed since the counters were taken or no summary exists for this mode."""
     path = os.path.join(ROOT, "profiles", "pair_%s_plummer262144.md" % prec)
     src = os.path.join(ROOT, "paper_1003_3896_amd", "csrc", "pair_kernel.h")
     if not os.path.exists(path):
@@ -79,6 +79,8 @@ def traffic_from_profile(prec):
             fields[k.strip()] = v.strip().strip("`")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if fields.get("kernel_source_sha256") != h:
+        return None
+    if tile is not None and fields.get("tile") != ",".join(str(v) for v in tile):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -101,6 +103,21 @@ def time_steps(sim, integrator, dt, steps, warmup, torch):
     nbody.nbody_timing_enable(sim.ctx, False)
     kms, nlaunch = nbody.nbody_timing_read(sim.ctx)
     return t1 - t0, kms, nlaunch
+
+
+def energy_fp64(sim):
+    """Library FP64 diagnostics of cluster 0: (E, E_int, Lz) with E_int = K_cm-frame + W."""
+    e = sim.energy(prec="fp64")[0].cpu().numpy()
+    K, W, Uext, E = e[0], e[1], e[2], e[3]
+    P = e[4:7]
+    M = e[13]
+    return E, K - 0.5 * float(P @ P) / M + W, e[9]
+
+
+def drift_report(e0, e1):
+    return {"dE_over_E0": float(abs(e1[0] - e0[0]) / abs(e0[0])),
+            "dE_over_Eint0": float(abs(e1[0] - e0[0]) / abs(e0[1])),
+            "dLz_over_Lz0": float(abs(e1[2] - e0[2]) / abs(e0[2])) if e0[2] != 0 else None}
 
 
 def per_cluster_baseline(batch, integrator, dt, steps, torch):
@@ -268,7 +285,11 @@ def main():
         del src, dst
 
     sim = nbody.Simulation(batch, prec)
+    from paper_1003_3896_amd import autotune
+    tile_used = nbody.nbody_get_tile(sim.ctx, prec, autotune.size_class(int(np.diff(batch.offsets).max())))
+    e_start = energy_fp64(sim) if args.workload in ("c1", "c2", "c3") else None
     wall, kms, nlaunch = time_steps(sim, integrator, dt, args.steps, args.warmup, torch)
+    e_end = energy_fp64(sim) if e_start is not None else None
     inter = inter_per_eval * evals_per_step * args.steps
     value = inter / wall / 1e9
     pair_ms = kms / max(nlaunch, 1)
@@ -280,7 +301,9 @@ def main():
         "peak": fam_peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / fam_peak, 4),
-        "traffic": traffic_from_profile(prec),
+        "traffic": traffic_from_profile(prec, tile_used),
+        "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
+                 "blocks_per_cu": tile_used[3]},
         "kernel": "pair (%s)" % prec,
         "kernel_ms": round(pair_ms, 4),
         "launches": nlaunch,
@@ -292,15 +315,17 @@ def main():
     sim.close()
 
     modes = {}
-    if not args.no_modes and args.workload == "c3":
-        for m in ("fp32c", "fp32", "fp64"):
+    if not args.no_modes and args.workload in ("c2", "c3"):
+        for m in (("fp32c", "fp32", "fp64") if args.workload == "c3" else ("fp64",)):
             if m == prec:
                 continue
             s2 = nbody.Simulation(batch, m)
-            w2, k2, n2 = time_steps(s2, integrator, dt, max(2, args.steps // 6), 1, torch)
             st = max(2, args.steps // 6)
-            modes[m] = {"G_interactions_per_s": round(inter_per_eval * st / w2 / 1e9, 2),
-                        "pair_kernel_ms": round(k2 / max(n2, 1), 4)}
+            a0 = energy_fp64(s2)
+            w2, k2, n2 = time_steps(s2, integrator, dt, st, 1, torch)
+            modes[m] = {"G_interactions_per_s": round(inter_per_eval * evals_per_step * st / w2 / 1e9, 2),
+                        "pair_kernel_ms": round(k2 / max(n2, 1), 4),
+                        "energy": dict(drift_report(a0, energy_fp64(s2)), steps=st + 1)}
             s2.close()
 
     result = {
@@ -329,8 +354,26 @@ def main():
         "pct_fp32_valu_peak": round(100 * value * 1e9 * FLOPS_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12), 2),
         "roofline": roofline,
     }
+    if e_start is not None:
+        result["energy"] = dict(drift_report(e_start, e_end), steps=args.steps + args.warmup,
+                                measured_in="fp64 library diagnostics")
     if modes:
         result["modes"] = modes
+    if args.workload in ("c1", "c2"):
+        # the same run with step graphs on and off (wall clock, no per-kernel events)
+        gres = {}
+        for use in (True, False):
+            s3 = nbody.Simulation(batch, prec)
+            nbody.nbody_use_graphs(s3.ctx, use)
+            s3.accel()
+            s3.step(integrator, dt, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s3.step(integrator, dt, args.steps)
+            torch.cuda.synchronize()
+            gres["graphs_on" if use else "graphs_off"] = round((time.perf_counter() - t0) / args.steps * 1e3, 4)
+            s3.close()
+        result["ms_per_step_graphs"] = gres
     if args.workload == "c4":
         bsteps = max(1, min(args.steps, 3))
         el = per_cluster_baseline(batch, integrator, dt, bsteps, torch)

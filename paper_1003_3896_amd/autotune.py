@@ -118,3 +118,36 @@ def apply(ctx, arch: str = "gfx950", path: str = CACHE, fixed_tile: Optional[Dic
         nbody.nbody_set_tile(ctx, prec, int(ncl), k, w, tile, cfg["bpc"])
         n += 1
     return n
+
+
+def representative(nclass: int):
+    """A workload of each size class: small ragged ensemble, the C4-like ensemble, one big cluster."""
+    from . import inputs
+    if nclass == 0:
+        return inputs.c4(B=256, lo=256, hi=2047)
+    if nclass == 1:
+        return inputs.c4()
+    return inputs.c3()
+
+
+def tune_all(precs=("fp32c", "fp32ds", "fp64"), classes=(0, 1, 2), path: str = CACHE, verbose: bool = True) -> Dict:
+    """Sweep every (precision family, size class) on its representative workload and cache the
+    fastest shape that passes the accuracy gate."""
+    out = {}
+    for ncl in classes:
+        batch = representative(ncl)
+        for prec in precs:
+            res = sweep(batch, prec)
+            b = best(res)
+            if b is None:
+                continue
+            save(prec, ncl, b, path=path, note="representative workload of class %d" % ncl)
+            out["%s/%d" % (prec, ncl)] = b
+            if verbose:
+                print("class %d %-6s k=%d w=%d T=%d bpc=%d  %.3f ms  err %.2e" % (
+                    ncl, prec, b["k"], b["w"], b["tile"], b["bpc"], b["ms"], b["err"]), flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    tune_all()

@@ -273,13 +273,16 @@ def nbody_last_error() -> str:
 class Simulation:
     """Device-resident state of one ragged batch plus its workspace; thin wrapper over the ABI."""
 
-    def __init__(self, batch, prec="fp32ds", device: int = 0, ctx: Optional[int] = None):
+    def __init__(self, batch, prec="fp32ds", device: int = 0, ctx: Optional[int] = None, tuned: bool = True):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)
         self.sys = system_from_batch(batch, prec)
         self.own_ctx = ctx is None
         self.ctx = nbody_create(device) if ctx is None else ctx
+        if tuned and self.own_ctx:
+            from . import autotune
+            autotune.apply(self.ctx)  # launch shapes from the autotuner's cache, if present
         self.ws_bytes = nbody_workspace_bytes(self.ctx, self.sys)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
         base = self.ws.data_ptr()
