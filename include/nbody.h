@@ -118,6 +118,13 @@ int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* 
                   double* acc, const double* kick_pre, const double* drift, const double* kick_post,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* nrounds (1..64) consecutive nbody_substep rounds in one call: coef is a HOST array
+ * [nrounds][B][3] of (kick_pre, drift, kick_post) per round and cluster, all finite.  Round r
+ * performs exactly what nbody_substep would with coef[r].  One table upload for all rounds; lets a
+ * batching caller chain rounds while the set of clusters does not change.  Asynchronous. */
+int nbody_substeps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                   double* acc, const double* coef, int32_t nrounds, void* ws, size_t ws_bytes, void* stream);
+
 /* nsteps (>= 0) steps of the 2nd-order leapfrog (Sect. 3.1) in kick-drift-kick form, step dt
  * (finite, any sign: a negative dt integrates backwards):
  *   vel += dt/2 acc;  pos += dt vel;  acc = A(pos);  vel += dt/2 acc

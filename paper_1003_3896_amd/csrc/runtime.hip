@@ -39,6 +39,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxRounds = 64;  // rounds one nbody_substeps call may carry
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // The 6th-order composition of Sect. 3.1 (Yoshida 1990, solution A): drift weights of the 7
@@ -60,7 +61,7 @@ const Sym6 kSym6;
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
   size_t cl, chunks, items, coef, counters, ref, partials, epart, rec_hi, rec_lo, rec64, pot, total;
-  size_t blob;  // bytes of the uploaded prefix [cl .. counters]
+  size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
 struct Plan {
@@ -176,11 +177,11 @@ Layout make_layout(int B, long long ntot, int nchunks) {
   o = align_up(o + sizeof(Chunk) * nchunks);
   L.items = o;
   o = align_up(o + sizeof(PairItem) * 4 * nchunks);  // the smallest item tile is 64 particles
-  L.coef = o;
-  o = align_up(o + sizeof(double) * 3 * B);
   L.counters = o;  // [B] chunk counters + 1 item counter
   o = align_up(o + sizeof(int) * (B + 1));
+  L.coef = o;  // [kMaxRounds][B][3] per-cluster stage coefficients; only the used rounds are uploaded
   L.blob = o;
+  o = align_up(o + sizeof(double) * 3 * (size_t)B * kMaxRounds);
   L.ref = o;
   o = align_up(o + sizeof(double4) * B);
   L.partials = o;
@@ -281,25 +282,27 @@ struct Prepared {
 };
 
 int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, const double* coef3,
-            Prepared& P, hipStream_t stream) {
+            Prepared& P, hipStream_t stream, int rounds = 1) {
   Plan& p = ctx->plan;
   const int fam = family_of(sys->prec);
   const TileCfg t = ctx->tiles[fam][size_class(p.maxn)];
   std::vector<PairItem> items;
   make_items(p, t, items);
-  // host blob: [clusters | chunks | items | coef | counters]
+  // host blob: [clusters | chunks | items | counters | coefficients of the used rounds]
   const Layout& L = p.L;
+  const size_t coef_bytes = coef3 ? sizeof(double) * 3 * (size_t)p.B * rounds : 0;
+  const size_t up = L.blob + coef_bytes;
   std::vector<unsigned char>& blob = ctx->blob;
-  blob.assign(L.blob, 0);
+  blob.assign(up, 0);
   memcpy(blob.data() + L.cl, p.cl.data(), sizeof(DevCluster) * p.B);
   memcpy(blob.data() + L.chunks, p.chunks.data(), sizeof(Chunk) * p.nchunks);
   memcpy(blob.data() + L.items, items.data(), sizeof(PairItem) * items.size());
-  if (coef3) memcpy(blob.data() + L.coef, coef3, sizeof(double) * 3 * p.B);
+  if (coef3) memcpy(blob.data() + L.coef, coef3, coef_bytes);
   int rc = NB_OK;
-  Slot* s = get_slot(ctx, L.blob, &rc);
+  Slot* s = get_slot(ctx, up, &rc);
   if (!s) return rc;
-  memcpy(s->host, blob.data(), L.blob);
-  HIP_TRY(hipMemcpyAsync(ws, s->host, L.blob, hipMemcpyHostToDevice, stream));
+  memcpy(s->host, blob.data(), up);
+  HIP_TRY(hipMemcpyAsync(ws, s->host, up, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(s->ev, stream));
   s->used = true;
 
@@ -622,35 +625,52 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
   return evaluate(ctx, P, false, pot != nullptr, false, s);
 }
 
-int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
-                  double* acc, const double* kick_pre, const double* drift, const double* kick_post, void* ws,
-                  size_t ws_bytes, void* stream) {
+int nbody_substeps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                   double* acc, const double* coef, int32_t nrounds, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
   int rc = build_plan(sys, ctx->plan);
   if (rc) return rc;
   if ((rc = check_state(ctx->plan, pos, vel, mass, acc, ws, ws_bytes))) return rc;
   if (!vel) return fail(NB_ERR_ARG, "vel is NULL");
-  if (!kick_pre || !drift || !kick_post) return fail(NB_ERR_ARG, "coefficient arrays must not be NULL");
+  if (!coef) return fail(NB_ERR_ARG, "coefficient table is NULL");
+  if (nrounds < 1 || nrounds > kMaxRounds) return fail(NB_ERR_ARG, "nrounds must be in [1, %d]", kMaxRounds);
   const int B = ctx->plan.B;
-  std::vector<double> coef(3 * (size_t)B);
-  for (int b = 0; b < B; ++b) {
-    if (!std::isfinite(kick_pre[b]) || !std::isfinite(drift[b]) || !std::isfinite(kick_post[b]))
-      return fail(NB_ERR_ARG, "coefficients of cluster %d are not finite", b);
-    coef[3 * b] = kick_pre[b];
-    coef[3 * b + 1] = drift[b];
-    coef[3 * b + 2] = kick_post[b];
-  }
+  for (size_t q = 0; q < 3 * (size_t)B * nrounds; ++q)
+    if (!std::isfinite(coef[q]))
+      return fail(NB_ERR_ARG, "coefficient %zu (round %zu, cluster %zu) is not finite", q, q / (3 * B), (q / 3) % B);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Prepared P;
-  if ((rc = prepare(ctx, sys, ws, ws_bytes, coef.data(), P, s))) return rc;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, coef, P, s, nrounds))) return rc;
   P.a.pos = pos;
   P.a.vel = vel;
   P.a.acc = acc;
   P.a.mass = mass;
   P.a.pot = nullptr;
-  return evaluate(ctx, P, true, false, true, s);
+  double* base = P.a.coef;
+  for (int r = 0; r < nrounds; ++r) {
+    P.a.coef = base + 3 * (size_t)B * r;
+    if ((rc = evaluate(ctx, P, true, false, true, s))) return rc;
+  }
+  return NB_OK;
+}
+
+int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
+                  double* acc, const double* kick_pre, const double* drift, const double* kick_post, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = check_system(sys);
+  if (rc) return rc;
+  if (!kick_pre || !drift || !kick_post) return fail(NB_ERR_ARG, "coefficient arrays must not be NULL");
+  const int B = sys->nclusters;
+  std::vector<double> coef(3 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    coef[3 * b] = kick_pre[b];
+    coef[3 * b + 1] = drift[b];
+    coef[3 * b + 2] = kick_post[b];
+  }
+  return nbody_substeps(ctx, sys, pos, vel, mass, acc, coef.data(), 1, ws, ws_bytes, stream);
 }
 
 int nbody_step_leapfrog(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,

@@ -24,7 +24,7 @@ EXPORTS = (
     "nbody_create", "nbody_destroy", "nbody_workspace_bytes", "nbody_accel", "nbody_substep",
     "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_last_error", "nbody_set_tile",
     "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions", "nbody_use_graphs",
-    "nbody_sym6_coefficients",
+    "nbody_sym6_coefficients", "nbody_substeps",
 )
 
 ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M", "_", "nonfinite")
@@ -81,6 +81,7 @@ def lib():
         L.nbody_workspace_bytes.restype = SZ
         L.nbody_accel.argtypes = [P, SYS, P, P, P, P, P, SZ, P]
         L.nbody_substep.argtypes = [P, SYS, P, P, P, P, P, P, P, P, SZ, P]
+        L.nbody_substeps.argtypes = [P, SYS, P, P, P, P, P, I32, P, SZ, P]
         L.nbody_step_leapfrog.argtypes = [P, SYS, P, P, P, P, D, I32, P, SZ, P]
         L.nbody_step_sym6.argtypes = [P, SYS, P, P, P, P, D, I32, P, SZ, P]
         L.nbody_energy.argtypes = [P, SYS, P, P, P, P, P, SZ, P]
@@ -95,7 +96,7 @@ def lib():
         L.nbody_interactions.restype = I64
         for name in ("nbody_create", "nbody_accel", "nbody_substep", "nbody_step_leapfrog", "nbody_step_sym6",
                      "nbody_energy", "nbody_set_tile", "nbody_get_tile", "nbody_timing_enable", "nbody_use_graphs",
-                     "nbody_sym6_coefficients",
+                     "nbody_sym6_coefficients", "nbody_substeps",
                      "nbody_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -210,6 +211,16 @@ def nbody_substep(ctx, sys: System, pos, vel, mass, acc, kick_pre, drift, kick_p
     _check(lib().nbody_substep(ctx, sys.ref(), _addr(pos), _addr(vel), _addr(mass), _addr(acc),
                                kp.ctypes.data_as(P), dr.ctypes.data_as(P), kq.ctypes.data_as(P), _addr(ws),
                                int(ws_bytes), _stream(stream)))
+
+
+def nbody_substeps(ctx, sys: System, pos, vel, mass, acc, coef, ws, ws_bytes: int, stream=None) -> None:
+    """coef: array [nrounds][B][3] of (kick_pre, drift, kick_post)."""
+    c = np.ascontiguousarray(coef, np.float64)
+    if c.ndim != 3 or c.shape[1:] != (sys.B, 3):
+        raise ValueError("coef must have shape (nrounds, B, 3)")
+    _check(lib().nbody_substeps(ctx, sys.ref(), _addr(pos), _addr(vel), _addr(mass), _addr(acc),
+                                c.ctypes.data_as(ctypes.c_void_p), int(c.shape[0]), _addr(ws), int(ws_bytes),
+                                _stream(stream)))
 
 
 def nbody_step_leapfrog(ctx, sys: System, pos, vel, mass, acc, dt: float, nsteps: int, ws, ws_bytes: int,

@@ -80,9 +80,14 @@ class Result:
 class _Active:
     req: Request
     offset: int
-    schedule: List[tuple]         # remaining (kick_pre, drift, kick_post) rounds
+    schedule: np.ndarray          # [rounds, 3] (kick_pre, drift, kick_post) of every round
+    cursor: int = 0               # next round to run
     energy0: Optional[np.ndarray] = None
     admitted_at: float = 0.0
+
+    @property
+    def left(self) -> int:
+        return self.schedule.shape[0] - self.cursor
 
 
 def stage_schedule(integrator: str, dt: float, steps: int, sym6: Optional[tuple] = None) -> List[tuple]:
@@ -160,10 +165,11 @@ class HipExecutor:
         offs[1:] = np.cumsum(sizes)
         return nbody.System(offs, np.asarray(eps, np.float64), np.asarray(fld, np.uint8), self.G, self.galaxy, prec)
 
-    def substep(self, sizes, eps, fld, kick_pre, drift, kick_post) -> None:
+    def substeps(self, sizes, eps, fld, coef) -> None:
+        """len(coef) rounds over the batch; coef is [rounds][B][3]."""
         sys = self._system(sizes, eps, fld, self.prec)
-        nbody.nbody_substep(self.ctx, sys, self.pos, self.vel, self.mass, self.acc, kick_pre, drift, kick_post,
-                            self.ws_addr, self.ws_bytes)
+        nbody.nbody_substeps(self.ctx, sys, self.pos, self.vel, self.mass, self.acc, coef, self.ws_addr,
+                             self.ws_bytes)
 
     def energy(self, offset: int, sizes, eps, fld) -> np.ndarray:
         """Diagnostics of the consecutive jobs starting at ``offset`` (one row each)."""
@@ -193,10 +199,16 @@ class Server:
     """Admission, per-round batching, retirement and latency bookkeeping (device work in the
     executor).  ``run(requests)`` replays arrival times against the wall clock."""
 
-    def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None):
+    def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None, round_budget_s: float = 4e-3,
+                 rate_estimate: float = 2e12, max_rounds_per_call: int = 64):
         self.ex = executor
         self.energy = energy
         self.clock = clock
+        # rounds are chained in one call while no job starts or ends, up to about round_budget_s of
+        # estimated device time (so a job arriving meanwhile waits at most about that long)
+        self.round_budget_s = round_budget_s
+        self.rate_estimate = rate_estimate
+        self.max_rounds_per_call = max_rounds_per_call
         self.sym6 = sym6 if sym6 is not None else nbody.nbody_sym6_coefficients()
         self.active: List[_Active] = []
         self.queue: List[Request] = []
@@ -233,7 +245,8 @@ class Server:
                 continue
             off = self.used()
             self.ex.load(off, req)
-            act = _Active(req, off, stage_schedule(req.integrator, req.dt, req.steps, self.sym6), admitted_at=now)
+            sched = np.array(stage_schedule(req.integrator, req.dt, req.steps, self.sym6), dtype=np.float64)
+            act = _Active(req, off, sched, admitted_at=now)
             self.active.append(act)
             new.append(act)
         if new and self.energy:
@@ -243,20 +256,28 @@ class Server:
                 a.energy0 = row
         return new
 
-    # -- one round -----------------------------------------------------------------------
-    def step_round(self) -> None:
+    # -- rounds --------------------------------------------------------------------------
+    def chain_length(self) -> int:
+        """Rounds to run in one call: until the first active job finishes, within the budget."""
         acts = self.active
-        kp = np.array([a.schedule[0][0] for a in acts])
-        dr = np.array([a.schedule[0][1] for a in acts])
-        kq = np.array([a.schedule[0][2] for a in acts])
-        self.ex.substep([a.req.n for a in acts], [a.req.eps for a in acts], [a.req.field for a in acts], kp, dr, kq)
-        self.rounds += 1
+        per_round = sum(a.req.n * a.req.n for a in acts) / self.rate_estimate
+        budget = max(1, int(self.round_budget_s / max(per_round, 1e-12)))
+        return max(1, min(min(a.left for a in acts), budget, self.max_rounds_per_call))
+
+    def step_rounds(self, rounds: int = 1) -> None:
+        acts = self.active
+        coef = np.stack([a.schedule[a.cursor:a.cursor + rounds] for a in acts], axis=1)  # [R][B][3]
+        self.ex.substeps([a.req.n for a in acts], [a.req.eps for a in acts], [a.req.field for a in acts], coef)
+        self.rounds += rounds
         for a in acts:
-            a.schedule.pop(0)
-            self.interactions += a.req.n * a.req.n
+            a.cursor += rounds
+            self.interactions += rounds * a.req.n * a.req.n
+
+    def step_round(self) -> None:
+        self.step_rounds(1)
 
     def _retire(self, now_fn) -> int:
-        done = [a for a in self.active if not a.schedule or a.req.jid in self.cancelled]
+        done = [a for a in self.active if a.left == 0 or a.req.jid in self.cancelled]
         if not done:
             return 0
         for a in done:
@@ -303,8 +324,11 @@ class Server:
                     r = self.queue.pop(0)
                     self.results[r.jid] = Result(r.jid, "rejected", reason="does not fit")
                 continue
-            self.step_round()
-            if any(not a.schedule for a in self.active) or self.cancelled:
+            nr = self.chain_length()
+            if max_rounds is not None:
+                nr = max(1, min(nr, max_rounds - self.rounds))
+            self.step_rounds(nr)
+            if any(a.left == 0 for a in self.active) or self.cancelled:
                 self.ex.sync()
                 self._retire(now_fn)
             if max_rounds is not None and self.rounds >= max_rounds:

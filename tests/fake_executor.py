@@ -23,6 +23,10 @@ class FakeExecutor:
         self.mass[offset:offset + n] = req.mass
         self.acc[offset:offset + n] = 0.0
 
+    def substeps(self, sizes, eps, fld, coef):
+        for r in range(len(coef)):
+            self.substep(sizes, eps, fld, coef[r][:, 0], coef[r][:, 1], coef[r][:, 2])
+
     def substep(self, sizes, eps, fld, kick_pre, drift, kick_post):
         self.calls.append(list(sizes))
         o = 0
