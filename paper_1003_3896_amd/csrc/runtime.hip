@@ -101,7 +101,7 @@ struct nbody_ctx {
   bool graphs = true;
   hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  StepGraph sg;
+  std::vector<StepGraph> gcache;  // small LRU cache of captured graphs (most recent last)
   TileCfg tiles[3][3];
   Slot slots[4];
   int next_slot = 0;
@@ -443,7 +443,9 @@ std::vector<unsigned char> graph_key(const Prepared& P, bool mask, int stages, F
     a.kick_pre = P.a.kick_pre;
     a.drift = P.a.drift;
     a.kick_post = P.a.kick_post;
+    a.coef = P.a.coef;
     put(&a.kick_pre, sizeof(double) * 3);
+    put(&a.coef, sizeof(a.coef));
     if (k == 0) {
       put(&a.cl, offsetof(Args, kick_pre));
       put(&a.G, sizeof(double));
@@ -459,10 +461,13 @@ std::vector<unsigned char> graph_key(const Prepared& P, bool mask, int stages, F
   return key;
 }
 
-// Launch nsteps replays of the captured step graph on the context's stream, ordered after the
-// caller's stream and before anything the caller issues next on it.
+constexpr size_t kMaxGraphs = 8;
+
+// Launch `replays` replays of the graph of `stages` evaluations (captured once per argument set and
+// cached) on the context's stream, ordered after the caller's stream and before anything the
+// caller issues next on it.
 template <class F>
-int replay_step_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t nsteps, hipStream_t s) {
+int replay_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t replays, hipStream_t s) {
   int rc;
   if (!ctx->gstream) {
     HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
@@ -470,17 +475,16 @@ int replay_step_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int
     HIP_TRY(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
   }
   std::vector<unsigned char> key = graph_key(P, ctx->plan.anymask, stages, set_stage);
-  StepGraph& g = ctx->sg;
-  if (!g.exec || g.key != key) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-    g.exec = nullptr;
-    g.graph = nullptr;
-    g.key.clear();
+  auto& gs = ctx->gcache;
+  size_t hit = gs.size();
+  for (size_t i = 0; i < gs.size(); ++i)
+    if (gs[i].key == key) hit = i;
+  if (hit == gs.size()) {
+    StepGraph g;
     HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < stages; ++k) {
       set_stage(k);
-      if ((rc = evaluate(ctx, P, true, false, k == stages - 1, ctx->gstream))) {
+      if ((rc = evaluate(ctx, P, true, false, P.a.coef != nullptr || k == stages - 1, ctx->gstream))) {
         hipGraph_t dead = nullptr;
         (void)hipStreamEndCapture(ctx->gstream, &dead);
         if (dead) (void)hipGraphDestroy(dead);
@@ -489,11 +493,25 @@ int replay_step_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int
     }
     HIP_TRY(hipStreamEndCapture(ctx->gstream, &g.graph));
     HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
-    g.key = key;
+    g.key = std::move(key);
+    if (gs.size() == kMaxGraphs) {
+      (void)hipStreamSynchronize(ctx->gstream);
+      (void)hipGraphExecDestroy(gs.front().exec);
+      (void)hipGraphDestroy(gs.front().graph);
+      gs.erase(gs.begin());
+    }
+    gs.push_back(std::move(g));
+    hit = gs.size() - 1;
+  } else if (hit != gs.size() - 1) {
+    StepGraph g = std::move(gs[hit]);
+    gs.erase(gs.begin() + hit);
+    gs.push_back(std::move(g));
+    hit = gs.size() - 1;
   }
+  hipGraphExec_t exec = gs[hit].exec;
   HIP_TRY(hipEventRecord(ctx->ev_in, s));
   HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
-  for (int32_t step = 0; step < nsteps; ++step) HIP_TRY(hipGraphLaunch(g.exec, ctx->gstream));
+  for (int32_t r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(exec, ctx->gstream));
   HIP_TRY(hipEventRecord(ctx->ev_out, ctx->gstream));
   HIP_TRY(hipStreamWaitEvent(s, ctx->ev_out, 0));
   return NB_OK;
@@ -533,7 +551,7 @@ int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel,
       }
     return NB_OK;
   }
-  return replay_step_graph(ctx, P, stages, set_stage, nsteps, s);
+  return replay_graph(ctx, P, stages, set_stage, nsteps, s);
 }
 
 }  // namespace
@@ -574,8 +592,10 @@ void nbody_destroy(nbody_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
-  if (ctx->sg.exec) (void)hipGraphExecDestroy(ctx->sg.exec);
-  if (ctx->sg.graph) (void)hipGraphDestroy(ctx->sg.graph);
+  for (StepGraph& g : ctx->gcache) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
@@ -649,11 +669,15 @@ int nbody_substeps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double*
   P.a.mass = mass;
   P.a.pot = nullptr;
   double* base = P.a.coef;
-  for (int r = 0; r < nrounds; ++r) {
-    P.a.coef = base + 3 * (size_t)B * r;
-    if ((rc = evaluate(ctx, P, true, false, true, s))) return rc;
+  auto set_round = [&](int r) { P.a.coef = base + 3 * (size_t)B * r; };
+  if (!ctx->graphs || ctx->timing || nrounds < 2) {
+    for (int r = 0; r < nrounds; ++r) {
+      set_round(r);
+      if ((rc = evaluate(ctx, P, true, false, true, s))) return rc;
+    }
+    return NB_OK;
   }
-  return NB_OK;
+  return replay_graph(ctx, P, nrounds, set_round, 1, s);
 }
 
 int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,

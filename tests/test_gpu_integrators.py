@@ -1,0 +1,107 @@
+"""Integrator paths on the GPU: chained substeps equal single substeps, the step functions equal
+their substep sequences, the C2-like configuration (Salpeter masses, galaxy field, sym6) follows the
+oracle, and pure-FP32 mode keeps the state on FP32 values."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import torch_dev
+from paper_1003_3896_amd import inputs, nbody
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch():
+    cl = []
+    for c, n in enumerate((300, 1000, 77)):
+        p, v, m = inputs.plummer(n, 810 + c, salpeter=(c == 1))
+        if c == 1:
+            p, v = inputs.on_orbit(p, v)
+        cl.append(inputs.single(p, v, m, 1e-3, c == 1))
+    return inputs.concat(cl)
+
+
+@pytest.mark.parametrize("prec", ["fp32ds", "fp64"])
+def test_substeps_equal_repeated_substep(prec):
+    """Chained rounds (captured into a graph and replayed with a new coefficient table each call)
+    equal single eager substeps, call after call, with other work in between."""
+    torch = torch_dev()
+    b = _batch()
+    rng = np.random.default_rng(5)
+    s1 = nbody.Simulation(b, prec)
+    s2 = nbody.Simulation(b, prec)
+    s1.accel()
+    s2.accel()
+    for call in range(3):
+        coef = rng.uniform(-0.002, 0.004, (5, b.B, 3))
+        nbody.nbody_substeps(s1.ctx, s1.sys, s1.pos, s1.vel, s1.mass, s1.acc, coef, s1.ws_addr, s1.ws_bytes)
+        for r in range(5):
+            s2.substep(coef[r, :, 0], coef[r, :, 1], coef[r, :, 2])
+        torch.cuda.synchronize()
+        for x, y in ((s1.pos, s2.pos), (s1.vel, s2.vel), (s1.acc, s2.acc)):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), call
+        s1.energy()
+        s2.energy()
+        torch.cuda.synchronize()
+
+
+def test_step_functions_equal_their_substep_sequences():
+    torch = torch_dev()
+    b = _batch()
+    dt = 1.0 / 700
+    d, k = nbody.nbody_sym6_coefficients()
+    for integ in ("leapfrog", "sym6"):
+        s1 = nbody.Simulation(b, "fp32ds")
+        s2 = nbody.Simulation(b, "fp32ds")
+        nbody.nbody_use_graphs(s1.ctx, False)
+        s1.accel()
+        s2.accel()
+        s1.step(integ, dt, 3)
+        if integ == "leapfrog":
+            rounds = [(0.5 * dt, dt, 0.5 * dt)] * 3
+        else:
+            rounds = [(k[s] * dt, d[s] * dt, k[7] * dt if s == 6 else 0.0) for s in range(7)] * 3
+        coef = np.array([[r] * b.B for r in rounds])
+        nbody.nbody_substeps(s2.ctx, s2.sys, s2.pos, s2.vel, s2.mass, s2.acc, coef, s2.ws_addr, s2.ws_bytes)
+        torch.cuda.synchronize()
+        assert np.array_equal(s1.pos.cpu().numpy(), s2.pos.cpu().numpy()), integ
+        assert np.array_equal(s1.vel.cpu().numpy(), s2.vel.cpu().numpy()), integ
+
+
+def test_c2_like_sym6_with_field_follows_oracle():
+    """N = 8192 with the C2 recipe (Salpeter masses, eps = 1e-4, galaxy, circular orbit at R = 8),
+    6 sym6 steps of dt = 2^-11: FP64 positions within 1e-10 of the oracle's, identical energy error;
+    FP32DS within 1e-7 and the same energy error to 1e-3 relative."""
+    torch_dev()
+    b = inputs.c2(n=8192)
+    dt = 2.0 ** -11
+    e0 = oracle.energy(b.pos, b.vel, b.mass, 1.0, 1e-4, True)
+    a0 = oracle.total_accel(b.pos, b.mass, 1.0, 1e-4, True)
+    rp, rv, _ = oracle.step(b.pos, b.vel, b.mass, a0, dt, 6, "sym6", 1.0, 1e-4, True)
+    de_ref = abs(oracle.energy(rp, rv, b.mass, 1.0, 1e-4, True)[3] - e0[3]) / abs(e0[3])
+    for prec, tol in (("fp64", 1e-10), ("fp32ds", 1e-7)):
+        s = nbody.Simulation(b, prec)
+        s.accel()
+        s.step("sym6", dt, 6)
+        pos = s.pos.cpu().numpy()
+        rel = np.abs(pos - rp).max() / np.abs(rp).max()
+        e = s.energy(prec="fp64")[0].cpu().numpy()
+        de = abs(e[3] - e0[3]) / abs(e0[3])
+        print("\n[C2-like %s] pos rel %.3e  dE/E0 %.3e (oracle %.3e)" % (prec, rel, de, de_ref), flush=True)
+        assert rel <= tol
+        if prec == "fp64":
+            assert abs(de - de_ref) <= 1e-3 * de_ref + 1e-14
+        else:
+            assert de <= 10 * de_ref + 1e-9
+        s.close()
+
+
+def test_pure_fp32_state_stays_fp32():
+    torch_dev()
+    b = _batch()
+    s = nbody.Simulation(b, "fp32")
+    s.accel()
+    s.step("sym6", 1.0 / 512, 2)
+    for t in (s.pos, s.vel, s.acc):
+        x = t.cpu().numpy()
+        assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
