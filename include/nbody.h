@@ -101,6 +101,11 @@ void nbody_destroy(nbody_ctx* ctx);
  * must not modify it while calls using it are in flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);
 
+/* An upper bound of nbody_workspace_bytes over every system of at most max_particles particles
+ * in at most max_clusters clusters (any sizes, modes, softenings): what a caller that changes its
+ * batch over time (the server) allocates once.  0 on invalid arguments. */
+size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters);
+
 /* Accelerations (Eq. 5 + external field of Eq. 3) of every particle of every cluster:
  *   acc[i] = a_i as defined above;  pot[i] = pair potential as defined above (pot may be NULL).
  * pos, mass: device, read.  acc, pot: device, written.  ws: device workspace of ws_bytes bytes.

@@ -44,4 +44,47 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return fma(y * e, t, y);
 }
 
+// Epilogue of one particle: scale by G, add the galaxy field, store, optional kick.
+__device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
+                                                double ax, double ay, double az, bool round32, int kick) {
+  ax *= a.G;
+  ay *= a.G;
+  az *= a.G;
+  if (round32) {
+    ax = (float)ax;
+    ay = (float)ay;
+    az = (float)az;
+  }
+  if (c.flags & kFlagField) {
+    double ex, ey, ez;
+    galaxy_accel(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
+    ax += ex;
+    ay += ey;
+    az += ez;
+    if (round32) {
+      ax = (float)ax;
+      ay = (float)ay;
+      az = (float)az;
+    }
+  }
+  if (a.acc) {
+    a.acc[3 * gi] = ax;
+    a.acc[3 * gi + 1] = ay;
+    a.acc[3 * gi + 2] = az;
+  }
+  if (kick) {
+    const double kp = a.coef ? a.coef[3 * cluster + 2] : a.kick_post;
+    double* v = a.vel + 3 * gi;
+    if (round32) {
+      v[0] = fmaf((float)kp, (float)ax, (float)v[0]);
+      v[1] = fmaf((float)kp, (float)ay, (float)v[1]);
+      v[2] = fmaf((float)kp, (float)az, (float)v[2]);
+    } else {
+      v[0] = fma(kp, ax, v[0]);
+      v[1] = fma(kp, ay, v[1]);
+      v[2] = fma(kp, az, v[2]);
+    }
+  }
+}
+
 }  // namespace nb

@@ -14,13 +14,16 @@ enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2 };
 
 // Per-cluster descriptor in device memory (uploaded with every call).
 struct DevCluster {
-  long long off;  // first particle of the cluster in the concatenated arrays
-  int n;          // particles
-  int flags;      // kFlagField | kFlagMaskSelf
-  double eps2;    // eps^2 in FP64
-  float eps2f;    // eps^2 rounded to FP32
-  int chunk0;     // first O(N) chunk of the cluster
-  int nchunks;    // O(N) chunks of the cluster
+  long long off;       // first particle of the cluster in the concatenated arrays
+  long long part_off;  // first row of the cluster's partial sums ([split][n] rows), when split > 1
+  int n;               // particles
+  int flags;           // kFlagField | kFlagMaskSelf
+  double eps2;         // eps^2 in FP64
+  float eps2f;         // eps^2 rounded to FP32
+  int chunk0;          // first O(N) chunk of the cluster
+  int nchunks;         // O(N) chunks of the cluster
+  int split;           // the j-sum of every particle is split into this many ranges (1 = none)
+  int jlen;            // sources per range (the last range may be shorter)
   int pad;
 };
 constexpr int kFlagField = 1;     // add the galaxy field
@@ -31,9 +34,9 @@ struct Chunk {
   int cluster, start, count, pad;
 };
 
-// Pair work item: one i-tile (kBlock * K particles starting at i0) of one cluster.
+// Pair work item: one i-tile of one cluster against one j-range (js) of it.
 struct PairItem {
-  int cluster, i0;
+  int cluster, i0, js, pad;
 };
 
 struct Galaxy {
@@ -51,6 +54,7 @@ struct Args {
   int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
   double4* partials;   // [nchunks] CoM partial sums (sum m x, sum m y, sum m z, sum m)
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
+  double4* part;       // partial sums (ax, ay, az, pot) of split clusters
   double* epart;       // [nchunks * 16] energy partials
   float4* rec_hi;      // [Ntot] packed j-records (FP32 families)
   float4* rec_lo;      // [Ntot] low parts (double-single family)
@@ -83,6 +87,7 @@ hipError_t launch_pack(const Args& a, hipStream_t s);
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
                        hipStream_t s);
 hipError_t launch_energy(const Args& a, hipStream_t s);
+hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s);
 
 bool tile_supported(int family, const TileCfg& t);
 // i-particles of one pair work item for a shape

@@ -43,49 +43,6 @@ struct PairLds<FAM_F64, T> {
   double4 r[T];
 };
 
-// Epilogue of one particle: scale by G, add the galaxy field, store, optional kick.
-__device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
-                                                double ax, double ay, double az, bool round32, int kick) {
-  ax *= a.G;
-  ay *= a.G;
-  az *= a.G;
-  if (round32) {
-    ax = (float)ax;
-    ay = (float)ay;
-    az = (float)az;
-  }
-  if (c.flags & kFlagField) {
-    double ex, ey, ez;
-    galaxy_accel(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
-    ax += ex;
-    ay += ey;
-    az += ez;
-    if (round32) {
-      ax = (float)ax;
-      ay = (float)ay;
-      az = (float)az;
-    }
-  }
-  if (a.acc) {
-    a.acc[3 * gi] = ax;
-    a.acc[3 * gi + 1] = ay;
-    a.acc[3 * gi + 2] = az;
-  }
-  if (kick) {
-    const double kp = a.coef ? a.coef[3 * cluster + 2] : a.kick_post;
-    double* v = a.vel + 3 * gi;
-    if (round32) {
-      v[0] = fmaf((float)kp, (float)ax, (float)v[0]);
-      v[1] = fmaf((float)kp, (float)ay, (float)v[1]);
-      v[2] = fmaf((float)kp, (float)az, (float)v[2]);
-    } else {
-      v[0] = fma(kp, ax, v[0]);
-      v[1] = fma(kp, ay, v[1]);
-      v[2] = fma(kp, az, v[2]);
-    }
-  }
-}
-
 // Takes the next work item for the whole block; returns -1 when none is left.
 __device__ __forceinline__ int next_item(const Args& a, int* s_item) {
   __syncthreads();
@@ -117,7 +74,7 @@ __device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, lo
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
 // red: [4 waves][64*K lanes][4] doubles (ax, ay, az, pot).
 template <int K, int W, bool POT>
-__device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluster& c, int cluster, int ibase,
+__device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluster& c, int cluster, int js, int ibase,
                                                   const double (&Ax)[K], const double (&Ay)[K], const double (&Az)[K],
                                                   const double (&Pt)[K], double* red, bool round32, int kick) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -150,6 +107,10 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
       }
     }
     if (li >= c.n) continue;
+    if (c.split > 1) {  // one j-range of a split cluster: leave the partial sums to the combine pass
+      a.part[c.part_off + (long long)js * c.n + li] = make_double4(ax, ay, az, pt);
+      continue;
+    }
     const long long gi = c.off + li;
     finish_particle(a, c, cluster, gi, ax, ay, az, round32, kick);
     if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
@@ -226,8 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
       Ax[k] = Ay[k] = Az[k] = Pt[k] = 0.0;
     }
     const float e2 = c.eps2f;
-    for (int j0 = 0; j0 < c.n; j0 += T) {
-      const int cnt = min(T, c.n - j0);
+    const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
+    for (int j0 = jb; j0 < je; j0 += T) {
+      const int cnt = min(T, je - j0);
       __syncthreads();
       load_tile<FAM, T>(a, sh, c.off + j0, cnt);
       __syncthreads();
@@ -273,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
         Pt[k] = pt[k];
       }
     }
-    reduce_and_finish<K, W, POT>(a, c, item.cluster, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+    reduce_and_finish<K, W, POT>(a, c, item.cluster, item.js, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
   }
 }
 
@@ -305,8 +267,9 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
       ax[k] = ay[k] = az[k] = pt[k] = 0.0;
     }
     const double e2 = c.eps2;
-    for (int j0 = 0; j0 < c.n; j0 += T) {
-      const int cnt = min(T, c.n - j0);
+    const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
+    for (int j0 = jb; j0 < je; j0 += T) {
+      const int cnt = min(T, je - j0);
       __syncthreads();
       load_tile<FAM_F64, T>(a, sh, c.off + j0, cnt);
       __syncthreads();
@@ -334,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
         }
       }
     }
-    reduce_and_finish<K, W, POT>(a, c, item.cluster, ibase, ax, ay, az, pt, red, false, kick);
+    reduce_and_finish<K, W, POT>(a, c, item.cluster, item.js, ibase, ax, ay, az, pt, red, false, kick);
   }
 }
 

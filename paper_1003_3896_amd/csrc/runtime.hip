@@ -60,7 +60,7 @@ const Sym6 kSym6;
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, items, coef, counters, ref, partials, epart, rec_hi, rec_lo, rec64, pot, total;
+  size_t cl, chunks, items, coef, counters, ref, partials, epart, rec_hi, rec_lo, rec64, pot, part, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -70,6 +70,7 @@ struct Plan {
   int nchunks = 0;
   int maxn = 0;
   bool anymask = false;
+  bool anysplit = false;
   std::vector<DevCluster> cl;
   std::vector<Chunk> chunks;
   Layout L{};
@@ -81,6 +82,15 @@ struct Slot {
   hipEvent_t ev = nullptr;
   bool used = false;
 };
+
+// j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
+// on their own (about 2^17 / N ranges, a power of two, at most 8), each range at least 512 sources.
+// Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
+int split_of(int n) {
+  int s = 1;
+  while (s < 8 && (long long)n * (2 * s) <= (1 << 17) && n / (2 * s) >= 512) s *= 2;
+  return s;
+}
 
 int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : 2; }
 int family_of(int prec) { return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ? FAM_DS : FAM_F32; }
@@ -168,7 +178,7 @@ int check_system(const nbody_system* sys) {
   return NB_OK;
 }
 
-Layout make_layout(int B, long long ntot, int nchunks) {
+Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
@@ -176,7 +186,7 @@ Layout make_layout(int B, long long ntot, int nchunks) {
   L.chunks = o;
   o = align_up(o + sizeof(Chunk) * nchunks);
   L.items = o;
-  o = align_up(o + sizeof(PairItem) * 4 * nchunks);  // the smallest item tile is 64 particles
+  o = align_up(o + sizeof(PairItem) * nitems_max);
   L.counters = o;  // [B] chunk counters + 1 item counter
   o = align_up(o + sizeof(int) * (B + 1));
   L.coef = o;  // [kMaxRounds][B][3] per-cluster stage coefficients; only the used rounds are uploaded
@@ -195,6 +205,8 @@ Layout make_layout(int B, long long ntot, int nchunks) {
   o = align_up(std::max(L.rec_lo + sizeof(float4) * ntot, o + sizeof(double4) * ntot));
   L.pot = o;
   o = align_up(o + sizeof(double) * ntot);
+  L.part = o;
+  o = align_up(o + sizeof(double4) * npart);
   L.total = o;
   return L;
 }
@@ -208,6 +220,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.chunks.clear();
   p.maxn = 0;
   p.anymask = false;
+  p.anysplit = false;
+  long long nitems_max = 0, npart = 0;
   for (int b = 0; b < p.B; ++b) {
     DevCluster& c = p.cl[b];
     c.off = sys->offsets[b];
@@ -223,12 +237,20 @@ int build_plan(const nbody_system* sys, Plan& p) {
     c.chunk0 = (int)p.chunks.size();
     c.nchunks = (c.n + kChunk - 1) / kChunk;
     for (int s = 0; s < c.n; s += kChunk) p.chunks.push_back(Chunk{b, s, std::min(kChunk, c.n - s), 0});
+    c.split = split_of(c.n);
+    c.jlen = (c.n + c.split - 1) / c.split;
+    c.part_off = c.split > 1 ? npart : 0;
+    if (c.split > 1) {
+      npart += (long long)c.split * c.n;
+      p.anysplit = true;
+    }
+    nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
     c.pad = 0;
     p.maxn = std::max(p.maxn, c.n);
   }
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks);
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart);
   return NB_OK;
 }
 
@@ -236,11 +258,13 @@ int build_plan(const nbody_system* sys, Plan& p) {
 void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::vector<int> order(p.B);
   for (int b = 0; b < p.B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].n > p.cl[y].n; });
+  // longest items first: the cost of an item is its j-range length
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].jlen > p.cl[y].jlen; });
   items.clear();
   const int tile = item_tile(t);
   for (int b : order)
-    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) items.push_back(PairItem{b, i0});
+    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile)
+      for (int js = 0; js < p.cl[b].split; ++js) items.push_back(PairItem{b, i0, js, 0});
 }
 
 Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
@@ -322,6 +346,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.rec_lo = reinterpret_cast<float4*>(w + L.rec_lo);
   a.rec64 = reinterpret_cast<double4*>(w + L.rec64);
   a.pot_ws = reinterpret_cast<double*>(w + L.pot);
+  a.part = reinterpret_cast<double4*>(w + L.part);
   a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
   a.G = sys->G;
   a.gal = Galaxy{sys->galaxy.Mb, sys->galaxy.ab, sys->galaxy.Md, sys->galaxy.ad,
@@ -372,7 +397,11 @@ int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, 
   }
   e = launch_pack(P.a, s);
   if (e != hipSuccess) return fail(NB_ERR_HIP, "pack kernel launch: %s", hipGetErrorString(e));
-  return pair(ctx, P, potmode, kick, s);
+  int rc = pair(ctx, P, potmode, kick, s);
+  if (rc || !ctx->plan.anysplit) return rc;
+  e = launch_combine(P.a, potmode, kick, s);
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "combine kernel launch: %s", hipGetErrorString(e));
+  return NB_OK;
 }
 
 int check_ptr(const void* p, const char* name) {
@@ -607,6 +636,20 @@ size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys) {
   Plan p;
   if (build_plan(sys, p)) return 0;
   return p.L.total;
+}
+
+size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
+  if (max_particles < 1 || max_clusters < 1 || max_clusters > max_particles) {
+    fail(NB_ERR_ARG, "need 1 <= max_clusters <= max_particles");
+    return 0;
+  }
+  const long long n = max_particles, B = max_clusters;
+  // sum ceil(n_c/256) <= B + n/256; sum ceil(n_c/64) split_c <= 8 (B + n/64);
+  // sum split_c n_c <= min(8 n, B 2^17) (split_c n_c <= 2^17 whenever split_c > 1)
+  const long long nchunks = B + n / kChunk;
+  const long long nitems = 8 * (B + n / 64);
+  const long long npart = std::min(8 * n, B * (1LL << 17));
+  return make_layout((int)B, n, (int)nchunks, nitems, npart).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {

@@ -24,7 +24,7 @@ EXPORTS = (
     "nbody_create", "nbody_destroy", "nbody_workspace_bytes", "nbody_accel", "nbody_substep",
     "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_last_error", "nbody_set_tile",
     "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions", "nbody_use_graphs",
-    "nbody_sym6_coefficients", "nbody_substeps",
+    "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max",
 )
 
 ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M", "_", "nonfinite")
@@ -79,6 +79,8 @@ def lib():
         L.nbody_destroy.restype = None
         L.nbody_workspace_bytes.argtypes = [P, SYS]
         L.nbody_workspace_bytes.restype = SZ
+        L.nbody_workspace_bytes_max.argtypes = [I64, I32]
+        L.nbody_workspace_bytes_max.restype = SZ
         L.nbody_accel.argtypes = [P, SYS, P, P, P, P, P, SZ, P]
         L.nbody_substep.argtypes = [P, SYS, P, P, P, P, P, P, P, P, SZ, P]
         L.nbody_substeps.argtypes = [P, SYS, P, P, P, P, P, I32, P, SZ, P]
@@ -185,6 +187,13 @@ def nbody_destroy(ctx: int) -> None:
 
 def nbody_workspace_bytes(ctx: Optional[int], sys: System) -> int:
     n = lib().nbody_workspace_bytes(ctx, sys.ref())
+    if n == 0:
+        raise NBodyError(NB_ERR_ARG, lib().nbody_last_error().decode())
+    return n
+
+
+def nbody_workspace_bytes_max(max_particles: int, max_clusters: int) -> int:
+    n = lib().nbody_workspace_bytes_max(int(max_particles), int(max_clusters))
     if n == 0:
         raise NBodyError(NB_ERR_ARG, lib().nbody_last_error().decode())
     return n

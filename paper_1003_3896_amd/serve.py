@@ -134,13 +134,9 @@ class HipExecutor:
         self.ws_addr = (self.ws.data_ptr() + 255) & ~255
 
     def _workspace_bound(self) -> int:
-        """Workspace for the worst admissible batch: B-1 single particles and one big cluster
-        (the most chunks and work items for a given particle count and cluster count)."""
-        B = self.max_clusters
-        sizes = [1] * (B - 1) + [max(1, self.capacity - (B - 1))]
-        offs = np.concatenate([[0], np.cumsum(sizes)])
-        return nbody.nbody_workspace_bytes(self.ctx, nbody.System(offs, np.ones(B), None, self.G, self.galaxy,
-                                                                  self.prec))
+        """Workspace for any admissible batch (the library's bound over all systems of at most
+        `capacity` particles in at most `max_clusters` clusters)."""
+        return nbody.nbody_workspace_bytes_max(self.capacity, self.max_clusters)
 
     def footprint_bytes(self) -> int:
         return STATE_BYTES_PER_PARTICLE * self.capacity + self.ws_bytes + 16 * 8 * self.max_clusters

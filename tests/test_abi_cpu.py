@@ -41,6 +41,14 @@ def test_workspace_bytes_and_interactions():
     # workspace does not depend on precision beyond the record area bound
     for p in ("fp32", "fp32c", "fp64"):
         assert nbody.nbody_workspace_bytes(None, s.with_prec(p)) == ws
+    # the batch-independent bound covers it, and covers adversarial batches of the same totals
+    bound = nbody.nbody_workspace_bytes_max(b.n, b.B)
+    assert bound >= ws
+    for sizes in ([1] * (b.B - 1) + [b.n - b.B + 1], [b.n // b.B] * (b.B - 1) + [b.n - (b.n // b.B) * (b.B - 1)],
+                  [4096] * (b.n // 4096)):
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        sys2 = nbody.System(offs, 1e-3)
+        assert nbody.nbody_workspace_bytes(None, sys2) <= nbody.nbody_workspace_bytes_max(offs[-1], len(sizes))
 
 
 @pytest.mark.parametrize("bad", [
@@ -88,3 +96,14 @@ def test_oracle_and_library_share_nothing():
                 assert "import oracle" not in txt and "nbody_oracle" not in txt and "liboracle" not in txt, f
     osrc = open(os.path.join(ROOT, "oracle", "nbody_oracle.c")).read()
     assert "nb_internal" not in osrc and "nbody.h" not in osrc
+
+
+def test_workspace_bound_holds_for_random_batches():
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        B = int(rng.integers(1, 40))
+        sizes = np.exp(rng.uniform(0, np.log(70000), B)).astype(np.int64) + 1
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3))
+        cap = int(offs[-1]) + int(rng.integers(0, 1000))
+        assert ws <= nbody.nbody_workspace_bytes_max(cap, B + int(rng.integers(0, 5)))
