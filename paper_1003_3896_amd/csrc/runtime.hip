@@ -491,6 +491,7 @@ std::vector<unsigned char> graph_key(const Prepared& P, bool mask, int stages, F
 }
 
 constexpr size_t kMaxGraphs = 8;
+constexpr int kGraphSteps = 8;
 
 // Launch `replays` replays of the graph of `stages` evaluations (captured once per argument set and
 // cached) on the context's stream, ordered after the caller's stream and before anything the
@@ -513,7 +514,7 @@ int replay_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t 
     HIP_TRY(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < stages; ++k) {
       set_stage(k);
-      if ((rc = evaluate(ctx, P, true, false, P.a.coef != nullptr || k == stages - 1, ctx->gstream))) {
+      if ((rc = evaluate(ctx, P, true, false, P.a.coef != nullptr || P.a.kick_post != 0.0, ctx->gstream))) {
         hipGraph_t dead = nullptr;
         (void)hipStreamEndCapture(ctx->gstream, &dead);
         if (dead) (void)hipGraphDestroy(dead);
@@ -580,7 +581,12 @@ int run_steps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel,
       }
     return NB_OK;
   }
-  return replay_graph(ctx, P, stages, set_stage, nsteps, s);
+  // one graph holds up to kGraphSteps steps (graph launches cost more than a few kernel launches)
+  const int gsteps = std::min<int>(nsteps, kGraphSteps);
+  auto set_multi = [&](int k) { set_stage(k % stages); };
+  if ((rc = replay_graph(ctx, P, gsteps * stages, set_multi, nsteps / gsteps, s))) return rc;
+  if (nsteps % gsteps) return replay_graph(ctx, P, (nsteps % gsteps) * stages, set_multi, 1, s);
+  return NB_OK;
 }
 
 }  // namespace

@@ -68,3 +68,17 @@ def test_graph_follows_new_state_buffers():
     e.step("leapfrog", 1.0 / 1024, 4)
     torch.cuda.synchronize()
     assert _same(g, e)
+
+
+def test_multi_step_graph_with_remainder():
+    """19 steps = two replays of an 8-step graph + a 3-step graph: bitwise the eager launches."""
+    torch = torch_dev()
+    b = inputs.c1()
+    for integ in ("leapfrog", "sym6"):
+        g, e = _pair(b, "fp32ds")
+        g.step(integ, 1.0 / 1024, 19)
+        e.step(integ, 1.0 / 1024, 19)
+        torch.cuda.synchronize()
+        assert _same(g, e), integ
+        g.close()
+        e.close()
