@@ -1,5 +1,5 @@
-// O(N) kernels of libnbody for gfx950: fused kick + drift + centre-of-mass partials, record
-// packing, and the energy / momentum diagnostics.  All are HBM-bound; one block of kBlock threads
+// O(N) kernels of libnbody for gfx950: fused kick + drift + centre-of-mass partials, and the
+// energy / momentum diagnostics.  All are HBM-bound; one block of kBlock threads
 // handles one chunk of kChunk particles of one cluster, so per-cluster reductions never mix
 // clusters.  Every reduction runs in a fixed order (bitwise reproducible); the last block of a
 // cluster to finish (device-scope atomic counter) combines the chunk partials and resets the
@@ -106,34 +106,6 @@ __global__ __launch_bounds__(kBlock) void k_update(Args a, int update, int com) 
   }
 }
 
-// Pack the j-records the pair kernel streams through LDS:
-//   NB_FP32   (x, y, z, m) rounded to FP32 (absolute coordinates)
-//   NB_FP32C  (x - ref, m) rounded to FP32
-//   NB_FP32DS hi = fl32(x - ref), lo = fl32((x - ref) - hi)   (double-single coordinates)
-//   NB_FP64   (x, y, z, m) in FP64 (absolute)
-// Also clears the pair kernel's work counter (this kernel always precedes it).
-__global__ __launch_bounds__(kBlock) void k_pack(Args a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.item_counter = 0;
-  const Chunk ch = a.chunks[blockIdx.x];
-  const int t = threadIdx.x;
-  if (t >= ch.count) return;
-  const DevCluster c = a.cl[ch.cluster];
-  const long long i = c.off + ch.start + t;
-  const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2], m = a.mass[i];
-  if (a.prec == NB_FP64) {
-    a.rec64[i] = make_double4(x, y, z, m);
-  } else if (a.prec == NB_FP32) {
-    a.rec_hi[i] = make_float4((float)x, (float)y, (float)z, (float)m);
-  } else {
-    const double4 r = a.ref[ch.cluster];
-    const double dx = x - r.x, dy = y - r.y, dz = z - r.z;
-    const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
-    a.rec_hi[i] = make_float4(hx, hy, hz, (float)m);
-    if (a.prec == NB_FP32DS)
-      a.rec_lo[i] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
-  }
-}
-
 // Diagnostics of one chunk (K, W, Uext, P, L, torque, M), then per cluster in the last block.
 __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
   __shared__ double sh[14][kBlock];
@@ -198,55 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
   }
 }
 
-// Sum the partial sums of the j-ranges of split clusters in range order and finish each particle
-// (scale by G, galaxy field, store, optional kick, optional potential), as the pair kernel does for
-// clusters that are not split.  Pure-FP32 mode adds the ranges in FP32.
-__global__ __launch_bounds__(kBlock) void k_combine(Args a, int potmode, int kick) {
-  const Chunk ch = a.chunks[blockIdx.x];
-  const DevCluster c = a.cl[ch.cluster];
-  const int t = threadIdx.x;
-  if (c.split <= 1 || t >= ch.count) return;
-  const int li = ch.start + t;
-  const long long gi = c.off + li;
-  const bool r32 = a.prec == NB_FP32;
-  double ax = 0.0, ay = 0.0, az = 0.0, pt = 0.0;
-  float fx = 0.0f, fy = 0.0f, fz = 0.0f, fp = 0.0f;
-  for (int s = 0; s < c.split; ++s) {
-    const double4 p = a.part[c.part_off + (long long)s * c.n + li];
-    if (r32) {
-      fx += (float)p.x;
-      fy += (float)p.y;
-      fz += (float)p.z;
-      fp += (float)p.w;
-    } else {
-      ax += p.x;
-      ay += p.y;
-      az += p.z;
-      pt += p.w;
-    }
-  }
-  if (r32) {
-    ax = fx;
-    ay = fy;
-    az = fz;
-    pt = fp;
-  }
-  finish_particle(a, c, ch.cluster, gi, ax, ay, az, r32, kick);
-  if (potmode && a.pot) a.pot[gi] = r32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
-}
-
-hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(a.nchunks), dim3(kBlock), 0, s, a, potmode ? 1 : 0, kick ? 1 : 0);
-  return hipGetLastError();
-}
-
 hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(a.nchunks), dim3(kBlock), 0, s, a, update ? 1 : 0, com ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack(const Args& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(a.nchunks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -44,6 +44,29 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return fma(y * e, t, y);
 }
 
+// j-record of particle gi as the pair kernels consume it:
+//   NB_FP32   (x, y, z, m) rounded to FP32 (absolute coordinates)
+//   NB_FP32C  (x - ref, m) rounded to FP32, ref = the cluster's FP64 centre of mass
+//   NB_FP32DS hi = fl32(x - ref), lo = fl32((x - ref) - hi)   (double-single coordinates)
+//   NB_FP64   (x, y, z, m) in FP64 (absolute)
+__device__ __forceinline__ void record32(const Args& a, long long gi, const double4& ref, float4& hi, float4& lo) {
+  const double x = a.pos[3 * gi], y = a.pos[3 * gi + 1], z = a.pos[3 * gi + 2];
+  const float m = (float)a.mass[gi];
+  if (a.prec == 0) {
+    hi = make_float4((float)x, (float)y, (float)z, m);
+    lo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
+  const double dx = x - ref.x, dy = y - ref.y, dz = z - ref.z;
+  const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
+  hi = make_float4(hx, hy, hz, m);
+  lo = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
+}
+
+__device__ __forceinline__ double4 record64(const Args& a, long long gi) {
+  return make_double4(a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], a.mass[gi]);
+}
+
 // Epilogue of one particle: scale by G, add the galaxy field, store, optional kick.
 __device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
                                                 double ax, double ay, double az, bool round32, int kick) {

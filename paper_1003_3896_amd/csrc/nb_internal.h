@@ -34,9 +34,10 @@ struct Chunk {
   int cluster, start, count, pad;
 };
 
-// Pair work item: one i-tile of one cluster against one j-range (js) of it.
+// Pair work item: one i-tile of one cluster against one j-range (js) of it; `tile` numbers the
+// i-tiles of split clusters (their arrival counters), -1 otherwise.
 struct PairItem {
-  int cluster, i0, js, pad;
+  int cluster, i0, js, tile;
 };
 
 struct Galaxy {
@@ -51,14 +52,13 @@ struct Args {
   const PairItem* items;
   int nitems;
   int* item_counter;   // dynamic work distribution of the persistent pair kernel
+  int* done_counter;   // blocks of the pair kernel that have finished (the last one resets both)
+  int* tile_counter;   // [tiles] j-ranges of a split i-tile that have finished
   int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
   double4* partials;   // [nchunks] CoM partial sums (sum m x, sum m y, sum m z, sum m)
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
   double4* part;       // partial sums (ax, ay, az, pot) of split clusters
   double* epart;       // [nchunks * 16] energy partials
-  float4* rec_hi;      // [Ntot] packed j-records (FP32 families)
-  float4* rec_lo;      // [Ntot] low parts (double-single family)
-  double4* rec64;      // [Ntot] packed j-records (FP64 family)
   double* pot_ws;      // [Ntot] pair potential scratch for the energy pass
   double* coef;        // [B*3] per-cluster (kick_pre, drift, kick_post), or null
   // state
@@ -83,11 +83,11 @@ struct TileCfg {
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
 hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s);
-hipError_t launch_pack(const Args& a, hipStream_t s);
+
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
                        hipStream_t s);
 hipError_t launch_energy(const Args& a, hipStream_t s);
-hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s);
+
 
 bool tile_supported(int family, const TileCfg& t);
 // i-particles of one pair work item for a shape

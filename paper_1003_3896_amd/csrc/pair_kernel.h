@@ -55,15 +55,18 @@ __device__ __forceinline__ int next_item(const Args& a, int* s_item) {
 // Loads one j-tile into LDS (padding beyond the cluster with zero-mass records far away, whose
 // terms are exactly 0 and never NaN).
 template <int FAM, int T>
-__device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, long long base, int cnt) {
+__device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, long long base, int cnt,
+                                          const double4& ref) {
   const int tid = threadIdx.x;
   if (tid >= T) return;
   if constexpr (FAM == FAM_F64) {
-    sh.r[tid] = tid < cnt ? a.rec64[base + tid] : make_double4(1e150, 1e150, 1e150, 0.0);
+    sh.r[tid] = tid < cnt ? record64(a, base + tid) : make_double4(1e150, 1e150, 1e150, 0.0);
   } else {
     if (tid < cnt) {
-      sh.hi[tid] = a.rec_hi[base + tid];
-      if constexpr (FAM == FAM_DS) sh.lo[tid] = a.rec_lo[base + tid];
+      float4 hi, lo;
+      record32(a, base + tid, ref, hi, lo);
+      sh.hi[tid] = hi;
+      if constexpr (FAM == FAM_DS) sh.lo[tid] = lo;
     } else {
       sh.hi[tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
       if constexpr (FAM == FAM_DS) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -71,10 +74,22 @@ __device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, lo
   }
 }
 
+// The last block of the launch to finish resets the work counters for the next launch.
+__device__ __forceinline__ void retire_block(const Args& a) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.done_counter, 1) == (int)gridDim.x - 1) {
+      *a.item_counter = 0;
+      *a.done_counter = 0;
+    }
+  }
+}
+
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
 // red: [4 waves][64*K lanes][4] doubles (ax, ay, az, pot).
 template <int K, int W, bool POT>
-__device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluster& c, int cluster, int js, int ibase,
+__device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluster& c, const PairItem& item, int ibase,
                                                   const double (&Ax)[K], const double (&Ay)[K], const double (&Az)[K],
                                                   const double (&Pt)[K], double* red, bool round32, int kick) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -91,29 +106,84 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
     }
     __syncthreads();
   }
+  double ax[K], ay[K], az[K], pt[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ax[k] = Ax[k];
+    ay[k] = Ay[k];
+    az[k] = Az[k];
+    pt[k] = POT ? Pt[k] : 0.0;
+    if constexpr (W > 1) {
+      if (sub != 0) continue;  // only the first wave of a group combines its group's partial sums
+#pragma unroll
+      for (int s = 1; s < W; ++s) {
+        const double* r = red + ((size_t)(wave + s) * 64 * K + k * 64 + lane) * 4;
+        ax[k] += r[0];
+        ay[k] += r[1];
+        az[k] += r[2];
+        if (POT) pt[k] += r[3];
+      }
+    }
+  }
+  if (c.split > 1) {
+    // one j-range of a split cluster: publish the partial sums; the item that completes the
+    // i-tile adds the ranges in range order and finishes the particles
+    if (sub == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int li = ibase + k * 64;
+        if (li < c.n) a.part[c.part_off + (long long)item.js * c.n + li] = make_double4(ax[k], ay[k], az[k], pt[k]);
+      }
+    }
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&a.tile_counter[item.tile], 1) == c.split - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) a.tile_counter[item.tile] = 0;
+    if (sub != 0) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int li = ibase + k * 64;
+      if (li >= c.n) continue;
+      double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+      float fx = 0.0f, fy = 0.0f, fz = 0.0f, fp = 0.0f;
+      for (int s = 0; s < c.split; ++s) {
+        const double4 p = a.part[c.part_off + (long long)s * c.n + li];
+        if (round32) {
+          fx += (float)p.x;
+          fy += (float)p.y;
+          fz += (float)p.z;
+          fp += (float)p.w;
+        } else {
+          sx += p.x;
+          sy += p.y;
+          sz += p.z;
+          sp += p.w;
+        }
+      }
+      if (round32) {
+        sx = fx;
+        sy = fy;
+        sz = fz;
+        sp = fp;
+      }
+      const long long gi = c.off + li;
+      finish_particle(a, c, item.cluster, gi, sx, sy, sz, round32, kick);
+      if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)sp) : -a.G * sp;
+    }
+    return;
+  }
   if (sub != 0) return;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int li = ibase + k * 64;
-    double ax = Ax[k], ay = Ay[k], az = Az[k], pt = POT ? Pt[k] : 0.0;
-    if constexpr (W > 1) {
-#pragma unroll
-      for (int s = 1; s < W; ++s) {
-        const double* r = red + ((size_t)(wave + s) * 64 * K + k * 64 + lane) * 4;
-        ax += r[0];
-        ay += r[1];
-        az += r[2];
-        if (POT) pt += r[3];
-      }
-    }
     if (li >= c.n) continue;
-    if (c.split > 1) {  // one j-range of a split cluster: leave the partial sums to the combine pass
-      a.part[c.part_off + (long long)js * c.n + li] = make_double4(ax, ay, az, pt);
-      continue;
-    }
     const long long gi = c.off + li;
-    finish_particle(a, c, cluster, gi, ax, ay, az, round32, kick);
-    if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
+    finish_particle(a, c, item.cluster, gi, ax[k], ay[k], az[k], round32, kick);
+    if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt[k]) : -a.G * pt[k];
   }
 }
 
@@ -163,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
     const PairItem item = a.items[it];
     const DevCluster c = a.cl[item.cluster];
+    const double4 ref = a.ref[item.cluster];
     const int ibase = item.i0 + grp * 64 * K + lane;
     float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K];
     float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K];
@@ -172,12 +243,12 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     for (int k = 0; k < K; ++k) {
       li[k] = ibase + k * 64;
       const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
-      const float4 p = a.rec_hi[gi];
+      float4 p, q;
+      record32(a, gi, ref, p, q);
       xi[k] = p.x;
       yi[k] = p.y;
       zi[k] = p.z;
       if constexpr (DS) {
-        const float4 q = a.rec_lo[gi];
         xl[k] = q.x;
         yl[k] = q.y;
         zl[k] = q.z;
@@ -191,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      load_tile<FAM, T>(a, sh, c.off + j0, cnt);
+      load_tile<FAM, T>(a, sh, c.off + j0, cnt, ref);
       __syncthreads();
       const int u0 = sub * TW;
       if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
@@ -235,8 +306,9 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
         Pt[k] = pt[k];
       }
     }
-    reduce_and_finish<K, W, POT>(a, c, item.cluster, item.js, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+    reduce_and_finish<K, W, POT>(a, c, item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
   }
+  retire_block(a);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -260,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     for (int k = 0; k < K; ++k) {
       li[k] = ibase + k * 64;
       const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
-      const double4 p = a.rec64[gi];
+      const double4 p = record64(a, gi);
       xi[k] = p.x;
       yi[k] = p.y;
       zi[k] = p.z;
@@ -271,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      load_tile<FAM_F64, T>(a, sh, c.off + j0, cnt);
+      load_tile<FAM_F64, T>(a, sh, c.off + j0, cnt, make_double4(0.0, 0.0, 0.0, 0.0));
       __syncthreads();
       const int u0 = sub * TW;
       const int mine = min(TW, ((cnt - u0 + 7) & ~7));
@@ -297,8 +369,9 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
         }
       }
     }
-    reduce_and_finish<K, W, POT>(a, c, item.cluster, item.js, ibase, ax, ay, az, pt, red, false, kick);
+    reduce_and_finish<K, W, POT>(a, c, item, ibase, ax, ay, az, pt, red, false, kick);
   }
+  retire_block(a);
 }
 
 // Kernel for one shape and flag set of a family (nullptr when not compiled in).

@@ -60,7 +60,7 @@ const Sym6 kSym6;
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, items, coef, counters, ref, partials, epart, rec_hi, rec_lo, rec64, pot, part, total;
+  size_t cl, chunks, items, counters, tiles, coef, ref, partials, epart, pot, part, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -178,7 +178,7 @@ int check_system(const nbody_system* sys) {
   return NB_OK;
 }
 
-Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart) {
+Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long ntiles, long long npart) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
@@ -187,8 +187,10 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + sizeof(Chunk) * nchunks);
   L.items = o;
   o = align_up(o + sizeof(PairItem) * nitems_max);
-  L.counters = o;  // [B] chunk counters + 1 item counter
-  o = align_up(o + sizeof(int) * (B + 1));
+  L.counters = o;  // [B] chunk counters, the item counter, the finished-blocks counter
+  o = align_up(o + sizeof(int) * (B + 2));
+  L.tiles = o;  // arrival counters of the i-tiles of split clusters
+  o = align_up(o + sizeof(int) * ntiles);
   L.coef = o;  // [kMaxRounds][B][3] per-cluster stage coefficients; only the used rounds are uploaded
   L.blob = o;
   o = align_up(o + sizeof(double) * 3 * (size_t)B * kMaxRounds);
@@ -198,11 +200,6 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + sizeof(double4) * nchunks);
   L.epart = o;
   o = align_up(o + sizeof(double) * 16 * nchunks);
-  // records: the FP32 and DS families use rec_hi (+ rec_lo), the FP64 family rec64; they share
-  L.rec_hi = o;
-  L.rec64 = o;
-  L.rec_lo = align_up(o + sizeof(float4) * ntot);
-  o = align_up(std::max(L.rec_lo + sizeof(float4) * ntot, o + sizeof(double4) * ntot));
   L.pot = o;
   o = align_up(o + sizeof(double) * ntot);
   L.part = o;
@@ -221,7 +218,7 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.maxn = 0;
   p.anymask = false;
   p.anysplit = false;
-  long long nitems_max = 0, npart = 0;
+  long long nitems_max = 0, ntiles = 0, npart = 0;
   for (int b = 0; b < p.B; ++b) {
     DevCluster& c = p.cl[b];
     c.off = sys->offsets[b];
@@ -245,12 +242,13 @@ int build_plan(const nbody_system* sys, Plan& p) {
       p.anysplit = true;
     }
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
+    if (c.split > 1) ntiles += (c.n + 63) / 64;
     c.pad = 0;
     p.maxn = std::max(p.maxn, c.n);
   }
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart);
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, ntiles, npart);
   return NB_OK;
 }
 
@@ -262,9 +260,13 @@ void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].jlen > p.cl[y].jlen; });
   items.clear();
   const int tile = item_tile(t);
+  int tid = 0;
   for (int b : order)
-    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile)
-      for (int js = 0; js < p.cl[b].split; ++js) items.push_back(PairItem{b, i0, js, 0});
+    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) {
+      const int split = p.cl[b].split;
+      for (int js = 0; js < split; ++js) items.push_back(PairItem{b, i0, js, split > 1 ? tid : -1});
+      if (split > 1) ++tid;
+    }
 }
 
 Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
@@ -339,12 +341,11 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.nitems = (int)items.size();
   a.chunk_counter = reinterpret_cast<int*>(w + L.counters);
   a.item_counter = reinterpret_cast<int*>(w + L.counters) + p.B;
+  a.done_counter = reinterpret_cast<int*>(w + L.counters) + p.B + 1;
+  a.tile_counter = reinterpret_cast<int*>(w + L.tiles);
   a.partials = reinterpret_cast<double4*>(w + L.partials);
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
-  a.rec_hi = reinterpret_cast<float4*>(w + L.rec_hi);
-  a.rec_lo = reinterpret_cast<float4*>(w + L.rec_lo);
-  a.rec64 = reinterpret_cast<double4*>(w + L.rec64);
   a.pot_ws = reinterpret_cast<double*>(w + L.pot);
   a.part = reinterpret_cast<double4*>(w + L.part);
   a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
@@ -395,13 +396,7 @@ int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, 
     e = launch_update(P.a, update, P.centred, s);
     if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
   }
-  e = launch_pack(P.a, s);
-  if (e != hipSuccess) return fail(NB_ERR_HIP, "pack kernel launch: %s", hipGetErrorString(e));
-  int rc = pair(ctx, P, potmode, kick, s);
-  if (rc || !ctx->plan.anysplit) return rc;
-  e = launch_combine(P.a, potmode, kick, s);
-  if (e != hipSuccess) return fail(NB_ERR_HIP, "combine kernel launch: %s", hipGetErrorString(e));
-  return NB_OK;
+  return pair(ctx, P, potmode, kick, s);
 }
 
 int check_ptr(const void* p, const char* name) {
@@ -654,8 +649,9 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   // sum split_c n_c <= min(8 n, B 2^17) (split_c n_c <= 2^17 whenever split_c > 1)
   const long long nchunks = B + n / kChunk;
   const long long nitems = 8 * (B + n / 64);
+  const long long ntiles = B + n / 64;
   const long long npart = std::min(8 * n, B * (1LL << 17));
-  return make_layout((int)B, n, (int)nchunks, nitems, npart).total;
+  return make_layout((int)B, n, (int)nchunks, nitems, ntiles, npart).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {
