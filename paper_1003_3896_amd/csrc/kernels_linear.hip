@@ -42,9 +42,11 @@ __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks)
 
 // Kick (v += kick_pre a) and drift (x += drift v) of one chunk; optionally the centre-of-mass
 // partial sums of the updated positions and, in the last block of a cluster, the cluster's
-// reference point ref = sum m x / sum m.
+// reference point ref = sum m x / sum m.  Always launched before the pair kernel, whose work
+// counter it clears.
 __global__ __launch_bounds__(kBlock) void k_update(Args a, int update, int com) {
   __shared__ double sh[4][kBlock];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.item_counter = 0;  // the pair kernel that follows starts at item 0
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
   const int t = threadIdx.x;
@@ -170,8 +172,52 @@ __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
   }
 }
 
+// Sum the partial sums of the j-ranges of split clusters in range order and finish each particle
+// (scale by G, galaxy field, store, optional kick, optional potential), as the pair kernel does for
+// clusters that are not split.  Pure-FP32 mode adds the ranges in FP32.
+__global__ __launch_bounds__(kBlock) void k_combine(Args a, int potmode, int kick) {
+  const Chunk ch = a.chunks[blockIdx.x];
+  const DevCluster c = a.cl[ch.cluster];
+  const int t = threadIdx.x;
+  if (c.split <= 1 || t >= ch.count) return;
+  const int li = ch.start + t;
+  const long long gi = c.off + li;
+  const bool r32 = a.prec == NB_FP32;
+  double ax = 0.0, ay = 0.0, az = 0.0, pt = 0.0;
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f, fp = 0.0f;
+  for (int s = 0; s < c.split; ++s) {
+    const double4 p = a.part[c.part_off + (long long)s * c.n + li];
+    if (r32) {
+      fx += (float)p.x;
+      fy += (float)p.y;
+      fz += (float)p.z;
+      fp += (float)p.w;
+    } else {
+      ax += p.x;
+      ay += p.y;
+      az += p.z;
+      pt += p.w;
+    }
+  }
+  if (r32) {
+    ax = fx;
+    ay = fy;
+    az = fz;
+    pt = fp;
+  }
+  finish_particle(a, c, ch.cluster, gi, ax, ay, az, r32, kick);
+  if (potmode && a.pot) a.pot[gi] = r32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
+}
+
+hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(a.nchunks), dim3(kBlock), 0, s, a, potmode ? 1 : 0, kick ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(a.nchunks), dim3(kBlock), 0, s, a, update ? 1 : 0, com ? 1 : 0);
+  // with neither update nor centre of mass one block suffices (it only clears the work counter)
+  hipLaunchKernelGGL(k_update, dim3(update || com ? a.nchunks : 1), dim3(kBlock), 0, s, a, update ? 1 : 0,
+                     com ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -34,10 +34,9 @@ struct Chunk {
   int cluster, start, count, pad;
 };
 
-// Pair work item: one i-tile of one cluster against one j-range (js) of it; `tile` numbers the
-// i-tiles of split clusters (their arrival counters), -1 otherwise.
+// Pair work item: one i-tile of one cluster against one j-range (js) of it.
 struct PairItem {
-  int cluster, i0, js, tile;
+  int cluster, i0, js, pad;
 };
 
 struct Galaxy {
@@ -52,8 +51,6 @@ struct Args {
   const PairItem* items;
   int nitems;
   int* item_counter;   // dynamic work distribution of the persistent pair kernel
-  int* done_counter;   // blocks of the pair kernel that have finished (the last one resets both)
-  int* tile_counter;   // [tiles] j-ranges of a split i-tile that have finished
   int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
   double4* partials;   // [nchunks] CoM partial sums (sum m x, sum m y, sum m z, sum m)
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
@@ -87,6 +84,7 @@ hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s);
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
                        hipStream_t s);
 hipError_t launch_energy(const Args& a, hipStream_t s);
+hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s);
 
 
 bool tile_supported(int family, const TileCfg& t);

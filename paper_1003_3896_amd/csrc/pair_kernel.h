@@ -74,18 +74,6 @@ __device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, lo
   }
 }
 
-// The last block of the launch to finish resets the work counters for the next launch.
-__device__ __forceinline__ void retire_block(const Args& a) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(a.done_counter, 1) == (int)gridDim.x - 1) {
-      *a.item_counter = 0;
-      *a.done_counter = 0;
-    }
-  }
-}
-
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
 // red: [4 waves][64*K lanes][4] doubles (ax, ay, az, pot).
 template <int K, int W, bool POT>
@@ -125,58 +113,18 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
       }
     }
   }
+  if (sub != 0) return;
   if (c.split > 1) {
-    // one j-range of a split cluster: publish the partial sums; the item that completes the
-    // i-tile adds the ranges in range order and finishes the particles
-    if (sub == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int li = ibase + k * 64;
-        if (li < c.n) a.part[c.part_off + (long long)item.js * c.n + li] = make_double4(ax[k], ay[k], az[k], pt[k]);
-      }
-    }
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&a.tile_counter[item.tile], 1) == c.split - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (threadIdx.x == 0) a.tile_counter[item.tile] = 0;
-    if (sub != 0) return;
+    // one j-range of a split cluster: the combine pass adds the ranges in range order and
+    // finishes the particles (kernel boundaries, not device-scope fences, order the two: a fence
+    // inside this persistent kernel would write back and invalidate the XCD's L2)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int li = ibase + k * 64;
-      if (li >= c.n) continue;
-      double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-      float fx = 0.0f, fy = 0.0f, fz = 0.0f, fp = 0.0f;
-      for (int s = 0; s < c.split; ++s) {
-        const double4 p = a.part[c.part_off + (long long)s * c.n + li];
-        if (round32) {
-          fx += (float)p.x;
-          fy += (float)p.y;
-          fz += (float)p.z;
-          fp += (float)p.w;
-        } else {
-          sx += p.x;
-          sy += p.y;
-          sz += p.z;
-          sp += p.w;
-        }
-      }
-      if (round32) {
-        sx = fx;
-        sy = fy;
-        sz = fz;
-        sp = fp;
-      }
-      const long long gi = c.off + li;
-      finish_particle(a, c, item.cluster, gi, sx, sy, sz, round32, kick);
-      if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)sp) : -a.G * sp;
+      if (li < c.n) a.part[c.part_off + (long long)item.js * c.n + li] = make_double4(ax[k], ay[k], az[k], pt[k]);
     }
     return;
   }
-  if (sub != 0) return;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int li = ibase + k * 64;
@@ -308,7 +256,6 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     }
     reduce_and_finish<K, W, POT>(a, c, item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
   }
-  retire_block(a);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -371,7 +318,6 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     }
     reduce_and_finish<K, W, POT>(a, c, item, ibase, ax, ay, az, pt, red, false, kick);
   }
-  retire_block(a);
 }
 
 // Kernel for one shape and flag set of a family (nullptr when not compiled in).

@@ -60,7 +60,7 @@ const Sym6 kSym6;
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, items, counters, tiles, coef, ref, partials, epart, pot, part, total;
+  size_t cl, chunks, items, counters, coef, ref, partials, epart, pot, part, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -178,7 +178,7 @@ int check_system(const nbody_system* sys) {
   return NB_OK;
 }
 
-Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long ntiles, long long npart) {
+Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
@@ -189,8 +189,6 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + sizeof(PairItem) * nitems_max);
   L.counters = o;  // [B] chunk counters, the item counter, the finished-blocks counter
   o = align_up(o + sizeof(int) * (B + 2));
-  L.tiles = o;  // arrival counters of the i-tiles of split clusters
-  o = align_up(o + sizeof(int) * ntiles);
   L.coef = o;  // [kMaxRounds][B][3] per-cluster stage coefficients; only the used rounds are uploaded
   L.blob = o;
   o = align_up(o + sizeof(double) * 3 * (size_t)B * kMaxRounds);
@@ -218,7 +216,7 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.maxn = 0;
   p.anymask = false;
   p.anysplit = false;
-  long long nitems_max = 0, ntiles = 0, npart = 0;
+  long long nitems_max = 0, npart = 0;
   for (int b = 0; b < p.B; ++b) {
     DevCluster& c = p.cl[b];
     c.off = sys->offsets[b];
@@ -242,13 +240,12 @@ int build_plan(const nbody_system* sys, Plan& p) {
       p.anysplit = true;
     }
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
-    if (c.split > 1) ntiles += (c.n + 63) / 64;
     c.pad = 0;
     p.maxn = std::max(p.maxn, c.n);
   }
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, ntiles, npart);
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart);
   return NB_OK;
 }
 
@@ -260,13 +257,9 @@ void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].jlen > p.cl[y].jlen; });
   items.clear();
   const int tile = item_tile(t);
-  int tid = 0;
   for (int b : order)
-    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) {
-      const int split = p.cl[b].split;
-      for (int js = 0; js < split; ++js) items.push_back(PairItem{b, i0, js, split > 1 ? tid : -1});
-      if (split > 1) ++tid;
-    }
+    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile)
+      for (int js = 0; js < p.cl[b].split; ++js) items.push_back(PairItem{b, i0, js, 0});
 }
 
 Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
@@ -341,8 +334,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.nitems = (int)items.size();
   a.chunk_counter = reinterpret_cast<int*>(w + L.counters);
   a.item_counter = reinterpret_cast<int*>(w + L.counters) + p.B;
-  a.done_counter = reinterpret_cast<int*>(w + L.counters) + p.B + 1;
-  a.tile_counter = reinterpret_cast<int*>(w + L.tiles);
+
   a.partials = reinterpret_cast<double4*>(w + L.partials);
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
@@ -389,14 +381,17 @@ int pair(nbody_ctx* ctx, const Prepared& P, bool potmode, bool kick, hipStream_t
 }
 
 // One force evaluation of the current positions, optionally preceded by kick+drift and
-// followed by a kick (the substep).  Kernel sequence: [update+CoM] -> pack -> pair.
+// followed by a kick (the substep).  Kernel sequence: update (kick, drift, centre of mass, work
+// counter) -> pair -> [combine of split clusters].
 int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, hipStream_t s) {
   hipError_t e;
-  if (update || P.centred) {
-    e = launch_update(P.a, update, P.centred, s);
-    if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
-  }
-  return pair(ctx, P, potmode, kick, s);
+  e = launch_update(P.a, update, P.centred, s);  // also clears the pair kernel's work counter
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
+  int rc = pair(ctx, P, potmode, kick, s);
+  if (rc || !ctx->plan.anysplit) return rc;
+  e = launch_combine(P.a, potmode, kick, s);
+  if (e != hipSuccess) return fail(NB_ERR_HIP, "combine kernel launch: %s", hipGetErrorString(e));
+  return NB_OK;
 }
 
 int check_ptr(const void* p, const char* name) {
@@ -649,9 +644,8 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   // sum split_c n_c <= min(8 n, B 2^17) (split_c n_c <= 2^17 whenever split_c > 1)
   const long long nchunks = B + n / kChunk;
   const long long nitems = 8 * (B + n / 64);
-  const long long ntiles = B + n / 64;
   const long long npart = std::min(8 * n, B * (1LL << 17));
-  return make_layout((int)B, n, (int)nchunks, nitems, ntiles, npart).total;
+  return make_layout((int)B, n, (int)nchunks, nitems, npart).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {
