@@ -54,22 +54,50 @@ __device__ __forceinline__ int next_item(const Args& a, int* s_item) {
 
 // Loads one j-tile into LDS (padding beyond the cluster with zero-mass records far away, whose
 // terms are exactly 0 and never NaN).
+// One thread's share of a j-tile, fetched from the FP64 state into registers ahead of its use so
+// that the global-memory latency overlaps the previous tile's arithmetic.
+struct TileRaw {
+  double x, y, z, m;
+  bool valid;
+};
+
+template <int T>
+__device__ __forceinline__ TileRaw fetch_tile(const Args& a, long long base, int cnt) {
+  const int tid = threadIdx.x;
+  TileRaw r;
+  r.valid = tid < T && tid < cnt;
+  if (r.valid) {
+    const long long g = base + tid;
+    r.x = a.pos[3 * g];
+    r.y = a.pos[3 * g + 1];
+    r.z = a.pos[3 * g + 2];
+    r.m = a.mass[g];
+  } else {
+    r.x = r.y = r.z = r.m = 0.0;
+  }
+  return r;
+}
+
+// Writes the fetched share into LDS as j-records (see record32/record64), padding beyond the
+// cluster with zero-mass records far away, whose terms are exactly 0 and never NaN.
 template <int FAM, int T>
-__device__ __forceinline__ void load_tile(const Args& a, PairLds<FAM, T>& sh, long long base, int cnt,
-                                          const double4& ref) {
+__device__ __forceinline__ void store_tile(const Args& a, PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref) {
   const int tid = threadIdx.x;
   if (tid >= T) return;
   if constexpr (FAM == FAM_F64) {
-    sh.r[tid] = tid < cnt ? record64(a, base + tid) : make_double4(1e150, 1e150, 1e150, 0.0);
+    sh.r[tid] = r.valid ? make_double4(r.x, r.y, r.z, r.m) : make_double4(1e150, 1e150, 1e150, 0.0);
   } else {
-    if (tid < cnt) {
-      float4 hi, lo;
-      record32(a, base + tid, ref, hi, lo);
-      sh.hi[tid] = hi;
-      if constexpr (FAM == FAM_DS) sh.lo[tid] = lo;
-    } else {
+    if (!r.valid) {
       sh.hi[tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
       if constexpr (FAM == FAM_DS) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else if (a.prec == 0) {
+      sh.hi[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.m);
+    } else {
+      const double dx = r.x - ref.x, dy = r.y - ref.y, dz = r.z - ref.z;
+      const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
+      sh.hi[tid] = make_float4(hx, hy, hz, (float)r.m);
+      if constexpr (FAM == FAM_DS)
+        sh.lo[tid] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
     }
   }
 }
@@ -207,11 +235,13 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     }
     const float e2 = c.eps2f;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
+    TileRaw raw = fetch_tile<T>(a, c.off + jb, min(T, je - jb));
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      load_tile<FAM, T>(a, sh, c.off + j0, cnt, ref);
+      store_tile<FAM, T>(a, sh, raw, ref);
       __syncthreads();
+      if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
       if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
 #pragma unroll 2
@@ -287,11 +317,13 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     }
     const double e2 = c.eps2;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
+    TileRaw raw = fetch_tile<T>(a, c.off + jb, min(T, je - jb));
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      load_tile<FAM_F64, T>(a, sh, c.off + j0, cnt, make_double4(0.0, 0.0, 0.0, 0.0));
+      store_tile<FAM_F64, T>(a, sh, raw, make_double4(0.0, 0.0, 0.0, 0.0));
       __syncthreads();
+      if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
       const int mine = min(TW, ((cnt - u0 + 7) & ~7));
       for (int u = u0; u < u0 + mine; u += 8) {
