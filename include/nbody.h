@@ -180,9 +180,12 @@ const char* nbody_last_error(void);
  *         tile/waves_per_group terms, so tile and waves_per_group change the last bits of FP32-mode
  *         results while k and blocks_per_cu never do
  *   blocks_per_cu  persistent blocks per compute unit (1..8)
+ *   phased  FP32 families only: full tiles are evaluated in groups of 8 pair terms whose
+ *         reciprocal square roots issue back to back (shapes (1,4,256), (2,2,256), (2,4,*));
+ *         the arithmetic of every term is unchanged
  * Returns NB_ERR_ARG for combinations that are not compiled in. */
 typedef struct {
-  int32_t k, waves_per_group, tile, blocks_per_cu;
+  int32_t k, waves_per_group, tile, blocks_per_cu, phased;
 } nbody_tile;
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);

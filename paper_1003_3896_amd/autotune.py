@@ -19,6 +19,8 @@ import numpy as np
 from . import nbody
 
 SHAPES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4)]
+# (k, w, tile) shapes that also have the rsq-phased loop (FP32 families)
+PHASED = {(1, 4, 256), (2, 2, 256), (2, 4, 128), (2, 4, 256)}
 TILES = [128, 256]
 BLOCKS_PER_CU = [2, 4, 8]
 FAMILY = {"fp32": "f32", "fp32c": "f32", "fp32ds": "ds", "fp64": "f64"}
@@ -56,23 +58,28 @@ def sweep(batch, prec: str, shapes=None, tiles=None, bpcs=None, reps: int = 3, s
     ref.close()
     sim = nbody.Simulation(batch, prec, device)
     out = []
+    cands = []
     for (k, w) in shapes:
         for t in tiles:
             for bpc in bpcs:
-                nbody.nbody_set_tile(sim.ctx, prec, nclass, k, w, t, bpc)
-                sim.accel()
-                torch.cuda.synchronize()
-                nbody.nbody_timing_read(sim.ctx)
-                nbody.nbody_timing_enable(sim.ctx, True)
-                for _ in range(reps):
-                    sim.accel()
-                torch.cuda.synchronize()
-                nbody.nbody_timing_enable(sim.ctx, False)
-                ms, n = nbody.nbody_timing_read(sim.ctx)
-                a = sim.acc.cpu().numpy()[rows]
-                err = float((np.linalg.norm(a - aref, axis=1) / scale).max())
-                out.append(dict(k=k, w=w, tile=t, bpc=bpc, ms=ms / max(n, 1), err=err,
-                                ok=err <= BOUND[prec], nclass=nclass))
+                cands.append((k, w, t, bpc, 0))
+                if prec != "fp64" and (k, w, t) in PHASED:
+                    cands.append((k, w, t, bpc, 1))
+    for (k, w, t, bpc, ph) in cands:
+        nbody.nbody_set_tile(sim.ctx, prec, nclass, k, w, t, bpc, ph)
+        sim.accel()
+        torch.cuda.synchronize()
+        nbody.nbody_timing_read(sim.ctx)
+        nbody.nbody_timing_enable(sim.ctx, True)
+        for _ in range(reps):
+            sim.accel()
+        torch.cuda.synchronize()
+        nbody.nbody_timing_enable(sim.ctx, False)
+        ms, n = nbody.nbody_timing_read(sim.ctx)
+        a = sim.acc.cpu().numpy()[rows]
+        err = float((np.linalg.norm(a - aref, axis=1) / scale).max())
+        out.append(dict(k=k, w=w, tile=t, bpc=bpc, phase=ph, ms=ms / max(n, 1), err=err,
+                        ok=err <= BOUND[prec], nclass=nclass))
     sim.close()
     return out
 
@@ -92,8 +99,8 @@ def load_cache(path: str = CACHE) -> Dict:
 def save(prec: str, nclass: int, cfg: Dict, arch: str = "gfx950", path: str = CACHE, note: str = "") -> None:
     data = load_cache(path)
     key = "%s/%s/%d" % (arch, FAMILY[prec], nclass)
-    data[key] = dict(k=cfg["k"], w=cfg["w"], tile=cfg["tile"], bpc=cfg["bpc"], ms=cfg["ms"], err=cfg["err"],
-                     note=note, when=time.strftime("%Y-%m-%d"))
+    data[key] = dict(k=cfg["k"], w=cfg["w"], tile=cfg["tile"], bpc=cfg["bpc"], phase=cfg.get("phase", 0),
+                     ms=cfg["ms"], err=cfg["err"], note=note, when=time.strftime("%Y-%m-%d"))
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
 
@@ -115,7 +122,8 @@ def apply(ctx, arch: str = "gfx950", path: str = CACHE, fixed_tile: Optional[Dic
             tile, w = fixed_tile[fam]
             if (k, w) not in SHAPES:
                 k = 1
-        nbody.nbody_set_tile(ctx, prec, int(ncl), k, w, tile, cfg["bpc"])
+        ph = cfg.get("phase", 0) if (k, w, tile) in PHASED and fam != "f64" else 0
+        nbody.nbody_set_tile(ctx, prec, int(ncl), k, w, tile, cfg["bpc"], ph)
         n += 1
     return n
 
@@ -144,8 +152,8 @@ def tune_all(precs=("fp32c", "fp32ds", "fp64"), classes=(0, 1, 2), path: str = C
             save(prec, ncl, b, path=path, note="representative workload of class %d" % ncl)
             out["%s/%d" % (prec, ncl)] = b
             if verbose:
-                print("class %d %-6s k=%d w=%d T=%d bpc=%d  %.3f ms  err %.2e" % (
-                    ncl, prec, b["k"], b["w"], b["tile"], b["bpc"], b["ms"], b["err"]), flush=True)
+                print("class %d %-6s k=%d w=%d T=%d bpc=%d phase=%d  %.3f ms  err %.2e" % (
+                    ncl, prec, b["k"], b["w"], b["tile"], b["bpc"], b["phase"], b["ms"], b["err"]), flush=True)
     return out
 
 

@@ -4,9 +4,11 @@
 namespace nb {
 
 bool tile_supported(int family, const TileCfg& t) {
-  (void)family;
   const bool kw = (t.k == 1 && (t.w == 1 || t.w == 2 || t.w == 4)) || (t.k == 2 && (t.w == 2 || t.w == 4));
-  return kw && (t.tile == 128 || t.tile == 256) && t.bpc >= 1 && t.bpc <= 8;
+  const bool ph = t.phase == 0 || (family != 2 && ((t.k == 1 && t.w == 4 && t.tile == 256) ||
+                                                   (t.k == 2 && t.w == 2 && t.tile == 256) ||
+                                                   (t.k == 2 && t.w == 4)));
+  return kw && ph && (t.tile == 128 || t.tile == 256) && t.bpc >= 1 && t.bpc <= 8;
 }
 
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,

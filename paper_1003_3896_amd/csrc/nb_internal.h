@@ -75,7 +75,7 @@ struct Args {
 // Pair-kernel launch shape: K i-particles per lane, W waves sharing an i-group, T j-records per
 // LDS tile, bpc persistent blocks per CU.
 struct TileCfg {
-  int k, w, tile, bpc;
+  int k, w, tile, bpc, phase;
 };
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.

@@ -196,7 +196,10 @@ __device__ __forceinline__ void interact32(const float4 pj, const float4 pl, con
   }
 }
 
-template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT>
+// PH: full tiles in phases of 8 pair terms (all coordinate differences and r^2, then the 8
+// v_rsq_f32 back to back, then the products and sums), fenced against compiler reordering, so the
+// transcendental ops of the waves sharing a SIMD can issue in pairs.
+template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT, bool PH = false>
 __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
   static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
   constexpr bool DS = FAM == FAM_DS;
@@ -243,7 +246,54 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
       __syncthreads();
       if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
-      if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
+      if (PH && cnt == T) {  // full tile in rsq-grouped phases
+        constexpr int BJ = 8 / K;
+        for (int u = u0; u < u0 + TW; u += BJ) {
+          float dx[BJ][K], dy[BJ][K], dz[BJ][K], r2[BJ][K], inv[BJ][K], mj[BJ];
+#pragma unroll
+          for (int v = 0; v < BJ; ++v) {
+            const float4 pj = sh.hi[u + v];
+            const float4 pl = sh.lo_at(u + v);
+            mj[v] = pj.w;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              dx[v][k] = pj.x - xi[k];
+              dy[v][k] = pj.y - yi[k];
+              dz[v][k] = pj.z - zi[k];
+              if constexpr (DS) {
+                dx[v][k] += pl.x - xl[k];
+                dy[v][k] += pl.y - yl[k];
+                dz[v][k] += pl.z - zl[k];
+              }
+              float q = fmaf(dx[v][k], dx[v][k], e2);
+              q = fmaf(dy[v][k], dy[v][k], q);
+              r2[v][k] = fmaf(dz[v][k], dz[v][k], q);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int v = 0; v < BJ; ++v)
+#pragma unroll
+            for (int k = 0; k < K; ++k) inv[v][k] = __builtin_amdgcn_rsqf(r2[v][k]);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int v = 0; v < BJ; ++v)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              const float sv = (mj[v] * inv[v][k]) * (inv[v][k] * inv[v][k]);
+              if (v & 1) {
+                bx[k] = fmaf(dx[v][k], sv, bx[k]);
+                by[k] = fmaf(dy[v][k], sv, by[k]);
+                bz[k] = fmaf(dz[v][k], sv, bz[k]);
+              } else {
+                ax[k] = fmaf(dx[v][k], sv, ax[k]);
+                ay[k] = fmaf(dy[v][k], sv, ay[k]);
+                az[k] = fmaf(dz[v][k], sv, az[k]);
+              }
+            }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
 #pragma unroll 2
         for (int u = u0; u < u0 + TW; u += 8) {
 #pragma unroll
@@ -371,9 +421,22 @@ PairFn pair_flags(bool fold, bool mask, bool pot) {
   }
 }
 
-// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)}, T in {128, 256}.
+// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)}, T in {128, 256}; the
+// rsq-phased full-tile loop for the FP32 families' main shapes, used for folded sums without the
+// self mask or the potential.
 template <int FAM>
 PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
+  if constexpr (FAM != FAM_F64) {
+    if (t.phase && fold && !mask && !pot) {
+#define NB_PHASED(KK, WW, TT) \
+  if (t.k == KK && t.w == WW && t.tile == TT) return k_pair32<FAM, KK, WW, TT, true, false, false, true>;
+      NB_PHASED(1, 4, 256)
+      NB_PHASED(2, 2, 256)
+      NB_PHASED(2, 4, 128)
+      NB_PHASED(2, 4, 256)
+#undef NB_PHASED
+    }
+  }
 #define NB_SHAPE(KK, WW, TT) \
   if (t.k == KK && t.w == WW && t.tile == TT) return pair_flags<FAM, KK, WW, TT>(fold, mask, pot);
   NB_SHAPE(1, 1, 128)

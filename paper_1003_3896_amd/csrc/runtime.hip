@@ -439,10 +439,10 @@ int check_state(const Plan& p, const void* pos, const void* vel, const void* mas
 void default_tiles(nbody_ctx* ctx) {
   for (int f = 0; f < 3; ++f)
     for (int c = 0; c < 3; ++c)
-      ctx->tiles[f][c] = c == 0 ? TileCfg{1, 4, 128, 8}
-                       : f == FAM_F32 ? TileCfg{1, 4, 128, 4}
-                       : f == FAM_DS  ? TileCfg{2, 4, 128, 8}
-                                      : TileCfg{2, 4, 256, 8};
+      ctx->tiles[f][c] = c == 0 ? TileCfg{1, 4, 128, 8, 0}
+                       : f == FAM_F32 ? TileCfg{2, 4, 256, 4, 0}
+                       : f == FAM_DS  ? TileCfg{2, 4, 256, 8, 0}
+                                      : TileCfg{2, 4, 256, 8, 0};
 }
 
 // Key of a captured step: every kernel argument except the per-stage coefficients, plus dt (via
@@ -780,11 +780,11 @@ int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
   if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
   if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
-  TileCfg t{tile.k, tile.waves_per_group, tile.tile, tile.blocks_per_cu};
+  TileCfg t{tile.k, tile.waves_per_group, tile.tile, tile.blocks_per_cu, tile.phased};
   const int fam = family_of(prec);
   if (!tile_supported(fam, t))
-    return fail(NB_ERR_ARG, "tile (k=%d, w=%d, tile=%d, blocks_per_cu=%d) is not compiled in", t.k, t.w, t.tile,
-                t.bpc);
+    return fail(NB_ERR_ARG, "tile (k=%d, w=%d, tile=%d, blocks_per_cu=%d, phased=%d) is not compiled in", t.k, t.w,
+                t.tile, t.bpc, t.phase);
   ctx->tiles[fam][nclass] = t;
   return NB_OK;
 }
@@ -798,6 +798,7 @@ int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_til
   tile->waves_per_group = t.w;
   tile->tile = t.tile;
   tile->blocks_per_cu = t.bpc;
+  tile->phased = t.phase;
   return NB_OK;
 }
 

@@ -54,7 +54,7 @@ class nbody_system(ctypes.Structure):
 
 class nbody_tile(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("phased", ctypes.c_int32)]
 
 
 _lib = None
@@ -249,16 +249,18 @@ def nbody_energy(ctx, sys: System, pos, vel, mass, out, ws, ws_bytes: int, strea
                               int(ws_bytes), _stream(stream)))
 
 
-def nbody_set_tile(ctx, prec, nclass: int, k: int, waves_per_group: int, tile: int, blocks_per_cu: int) -> None:
+def nbody_set_tile(ctx, prec, nclass: int, k: int, waves_per_group: int, tile: int, blocks_per_cu: int,
+                   phased: int = 0) -> None:
     prec = PREC[prec] if isinstance(prec, str) else prec
-    _check(lib().nbody_set_tile(ctx, int(prec), int(nclass), nbody_tile(k, waves_per_group, tile, blocks_per_cu)))
+    _check(lib().nbody_set_tile(ctx, int(prec), int(nclass),
+                                nbody_tile(k, waves_per_group, tile, blocks_per_cu, int(phased))))
 
 
 def nbody_get_tile(ctx, prec, nclass: int):
     prec = PREC[prec] if isinstance(prec, str) else prec
     t = nbody_tile()
     _check(lib().nbody_get_tile(ctx, int(prec), int(nclass), ctypes.byref(t)))
-    return (t.k, t.waves_per_group, t.tile, t.blocks_per_cu)
+    return (t.k, t.waves_per_group, t.tile, t.blocks_per_cu, t.phased)
 
 
 def nbody_sym6_coefficients():

@@ -108,7 +108,7 @@ class HipExecutor:
     """Device side of the server: a particle arena, its workspace and the library context."""
 
     def __init__(self, capacity: int, max_clusters: int, prec: str = "fp32ds", device: int = 0,
-                 energy_prec: str = "fp64", tile=(1, 4, 128, 8), G: float = 1.0, galaxy=None):
+                 energy_prec: str = "fp64", tile=(1, 4, 128, 8, 0), G: float = 1.0, galaxy=None):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", device)

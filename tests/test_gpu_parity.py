@@ -210,3 +210,28 @@ def test_full_size_c3_sampled_rows():
         mom = np.abs((b.mass[:, None] * a).sum(0)).max() / (b.mass[:, None] * np.abs(a)).sum()
         assert mom < (1e-12 if prec == "fp64" else 1e-6)
         sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32ds", "fp32c"])
+@pytest.mark.parametrize("tile", [(2, 4, 256, 4, 1), (1, 4, 256, 8, 1), (2, 2, 256, 4, 1), (2, 4, 128, 8, 1),
+                                  (1, 1, 128, 2, 0), (1, 2, 256, 8, 0)])
+def test_launch_shapes_agree(prec, tile):
+    """Every launch shape (including the rsq-phased loop) meets the same accuracy bound; shapes with
+    the same tile and waves per group give bitwise the same result."""
+    torch_dev()
+    from paper_1003_3896_amd import nbody
+    p, v, m = inputs.plummer(3000, 4321)
+    b = inputs.single(p, v, m, 1e-3)
+    sim = make_sim(b, prec)
+    for ncl in range(3):
+        nbody.nbody_set_tile(sim.ctx, prec, ncl, *tile)
+    a = sim.accel().cpu().numpy().copy()
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    if prec in TOL:
+        assert err.max() <= TOL[prec]
+    assert np.median(err) <= TOL_MEDIAN[prec]
+    if tile[4] == 1:  # the phased loop does the same arithmetic per term as the plain one
+        for ncl in range(3):
+            nbody.nbody_set_tile(sim.ctx, prec, ncl, *tile[:4], 0)
+        assert np.array_equal(sim.accel().cpu().numpy(), a)
