@@ -40,21 +40,22 @@ __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks)
   return last;
 }
 
-// Kick (v += kick_pre a) and drift (x += drift v) of one chunk; optionally the centre-of-mass
-// partial sums of the updated positions and, in the last block of a cluster, the cluster's
-// reference point ref = sum m x / sum m.  Always launched before the pair kernel, whose work
-// counter it clears.
-__global__ __launch_bounds__(kBlock) void k_update(Args a, int update, int com) {
-  __shared__ double sh[4][kBlock];
+// Kick (v += kick_pre a) and drift (x += drift v) of one chunk (when `update`), then per cluster
+// the reference point ref = sum m x / sum m of the (new) positions and whether all masses are
+// equal (mconst = that mass, else 0), combined in the last block of the cluster.  Always launched
+// before the pair kernel, whose work counter it clears.
+__global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
+  __shared__ double sh[5][kBlock];
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.item_counter = 0;  // the pair kernel that follows starts at item 0
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
   const int t = threadIdx.x;
   const bool valid = t < ch.count;
   const long long i = c.off + ch.start + t;
-  double x[3] = {0.0, 0.0, 0.0}, m = 0.0;
+  double x[3] = {0.0, 0.0, 0.0}, m = 0.0, odd = 0.0;
   if (valid) {
     m = a.mass[i];
+    odd = m != a.mass[c.off] ? 1.0 : 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) x[d] = a.pos[3 * i + d];
     if (update) {
@@ -85,25 +86,23 @@ __global__ __launch_bounds__(kBlock) void k_update(Args a, int update, int com) 
       }
     }
   }
-  if (!com) return;
-  double val[4] = {m * x[0], m * x[1], m * x[2], m};
-  block_reduce<4>(val, sh);
-  if (t == 0) a.partials[blockIdx.x] = make_double4(val[0], val[1], val[2], val[3]);
+  double val[5] = {m * x[0], m * x[1], m * x[2], m, odd};
+  block_reduce<5>(val, sh);
+  if (t == 0)
+    for (int q = 0; q < 5; ++q) a.partials[(size_t)blockIdx.x * 5 + q] = val[q];
   if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
-  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int q = t; q < c.nchunks; q += kBlock) {
-    const double4 p = a.partials[c.chunk0 + q];
-    tot[0] += p.x;
-    tot[1] += p.y;
-    tot[2] += p.z;
-    tot[3] += p.w;
+    const double* p = a.partials + (size_t)(c.chunk0 + q) * 5;
+    for (int r = 0; r < 5; ++r) tot[r] += p[r];
   }
   __syncthreads();
-  block_reduce<4>(tot, sh);
+  block_reduce<5>(tot, sh);
   if (t == 0) {
     const double M = tot[3];
     a.ref[ch.cluster] = M > 0.0 ? make_double4(tot[0] / M, tot[1] / M, tot[2] / M, M)
                                 : make_double4(0.0, 0.0, 0.0, 0.0);
+    a.mconst[ch.cluster] = tot[4] == 0.0 ? a.mass[c.off] : 0.0;
     a.chunk_counter[ch.cluster] = 0;
   }
 }
@@ -214,10 +213,8 @@ hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s) {
-  // with neither update nor centre of mass one block suffices (it only clears the work counter)
-  hipLaunchKernelGGL(k_update, dim3(update || com ? a.nchunks : 1), dim3(kBlock), 0, s, a, update ? 1 : 0,
-                     com ? 1 : 0);
+hipError_t launch_update(const Args& a, bool update, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(a.nchunks), dim3(kBlock), 0, s, a, update ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -52,7 +52,8 @@ struct Args {
   int nitems;
   int* item_counter;   // dynamic work distribution of the persistent pair kernel
   int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
-  double4* partials;   // [nchunks] CoM partial sums (sum m x, sum m y, sum m z, sum m)
+  double* partials;    // [nchunks][5] chunk sums: m x, m y, m z, m, count of masses != the cluster's first
+  double* mconst;      // [B] the common mass of a cluster whose masses are all equal, else 0
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
   double4* part;       // partial sums (ax, ay, az, pot) of split clusters
   double* epart;       // [nchunks * 16] energy partials
@@ -79,7 +80,7 @@ struct TileCfg {
 };
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
-hipError_t launch_update(const Args& a, bool update, bool com, hipStream_t s);
+hipError_t launch_update(const Args& a, bool update, hipStream_t s);
 
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
                        hipStream_t s);

@@ -52,8 +52,6 @@ __device__ __forceinline__ int next_item(const Args& a, int* s_item) {
   return it < a.nitems ? it : -1;
 }
 
-// Loads one j-tile into LDS (padding beyond the cluster with zero-mass records far away, whose
-// terms are exactly 0 and never NaN).
 // One thread's share of a j-tile, fetched from the FP64 state into registers ahead of its use so
 // that the global-memory latency overlaps the previous tile's arithmetic.
 struct TileRaw {
@@ -79,23 +77,27 @@ __device__ __forceinline__ TileRaw fetch_tile(const Args& a, long long base, int
 }
 
 // Writes the fetched share into LDS as j-records (see record32/record64), padding beyond the
-// cluster with zero-mass records far away, whose terms are exactly 0 and never NaN.
+// cluster with zero-weight records far away, whose terms are exactly 0 and never NaN.  The weight
+// is the mass, or 1 when the cluster's masses are all equal (eq: the sums leave the mass out and
+// are scaled by it once at the end).
 template <int FAM, int T>
-__device__ __forceinline__ void store_tile(const Args& a, PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref) {
+__device__ __forceinline__ void store_tile(const Args& a, PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref,
+                                           bool eq) {
   const int tid = threadIdx.x;
   if (tid >= T) return;
+  const double w = eq ? 1.0 : r.m;
   if constexpr (FAM == FAM_F64) {
-    sh.r[tid] = r.valid ? make_double4(r.x, r.y, r.z, r.m) : make_double4(1e150, 1e150, 1e150, 0.0);
+    sh.r[tid] = r.valid ? make_double4(r.x, r.y, r.z, w) : make_double4(1e150, 1e150, 1e150, 0.0);
   } else {
     if (!r.valid) {
       sh.hi[tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
       if constexpr (FAM == FAM_DS) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     } else if (a.prec == 0) {
-      sh.hi[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.m);
+      sh.hi[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)w);
     } else {
       const double dx = r.x - ref.x, dy = r.y - ref.y, dz = r.z - ref.z;
       const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
-      sh.hi[tid] = make_float4(hx, hy, hz, (float)r.m);
+      sh.hi[tid] = make_float4(hx, hy, hz, (float)w);
       if constexpr (FAM == FAM_DS)
         sh.lo[tid] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
     }
@@ -168,8 +170,9 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
 
 // One j-record against the K i-particles of this lane:
 //   d = x_j - x_i (double-single: (hi_j - hi_i) + (lo_j - lo_i)),  r2 = |d|^2 + eps^2,
-//   s = m_j r2^{-3/2},  a += s d,  and with POT  pot += m_j r2^{-1/2} for j != i.
-template <bool DS, int K, bool MASK, bool POT>
+//   s = m_j r2^{-3/2},  a += s d,  and with POT  pot += m_j r2^{-1/2} for j != i
+// (EQ: all masses of the cluster are equal, m_j is left out here and multiplied in once later).
+template <bool DS, int K, bool MASK, bool POT, bool EQ>
 __device__ __forceinline__ void interact32(const float4 pj, const float4 pl, const float (&xi)[K], const float (&yi)[K],
                                            const float (&zi)[K], const float (&xl)[K], const float (&yl)[K],
                                            const float (&zl)[K], float e2, float (&ax)[K], float (&ay)[K],
@@ -186,13 +189,80 @@ __device__ __forceinline__ void interact32(const float4 pj, const float4 pl, con
     r2 = fmaf(dy, dy, r2);
     r2 = fmaf(dz, dz, r2);
     const float inv = __builtin_amdgcn_rsqf(r2);
-    const float mi = pj.w * inv;
+    const float mi = EQ ? inv : pj.w * inv;  // equal masses: m_j is applied once, after the sum
     float s = mi * (inv * inv);
     if (MASK) s = r2 > 0.0f ? s : 0.0f;
     ax[k] = fmaf(dx, s, ax[k]);
     ay[k] = fmaf(dy, s, ay[k]);
     az[k] = fmaf(dz, s, az[k]);
     if (POT) pt[k] += (j != li[k]) ? mi : 0.0f;
+  }
+}
+
+// The pair terms of this wave's share [u0, u0 + TW) of one full LDS tile (T records).
+template <int FAM, int K, int TW, int T, bool MASK, bool POT, bool PH, bool EQ>
+__device__ __forceinline__ void full_tile_terms(const PairLds<FAM, T>& sh, int u0, int j0, const float (&xi)[K],
+                                           const float (&yi)[K], const float (&zi)[K], const float (&xl)[K],
+                                           const float (&yl)[K], const float (&zl)[K], float e2, float (&ax)[K],
+                                           float (&ay)[K], float (&az)[K], float (&bx)[K], float (&by)[K],
+                                           float (&bz)[K], float (&pt)[K], const int (&li)[K]) {
+  constexpr bool DS = FAM == FAM_DS;
+  if (PH) {  // rsq-grouped phases
+    constexpr int BJ = 8 / K;
+    for (int u = u0; u < u0 + TW; u += BJ) {
+      float dx[BJ][K], dy[BJ][K], dz[BJ][K], r2[BJ][K], inv[BJ][K], mj[BJ];
+#pragma unroll
+      for (int v = 0; v < BJ; ++v) {
+        const float4 pj = sh.hi[u + v];
+        const float4 pl = sh.lo_at(u + v);
+        mj[v] = pj.w;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          dx[v][k] = pj.x - xi[k];
+          dy[v][k] = pj.y - yi[k];
+          dz[v][k] = pj.z - zi[k];
+          if constexpr (DS) {
+            dx[v][k] += pl.x - xl[k];
+            dy[v][k] += pl.y - yl[k];
+            dz[v][k] += pl.z - zl[k];
+          }
+          float q = fmaf(dx[v][k], dx[v][k], e2);
+          q = fmaf(dy[v][k], dy[v][k], q);
+          r2[v][k] = fmaf(dz[v][k], dz[v][k], q);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < BJ; ++v)
+#pragma unroll
+        for (int k = 0; k < K; ++k) inv[v][k] = __builtin_amdgcn_rsqf(r2[v][k]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int v = 0; v < BJ; ++v)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float sv = (EQ ? inv[v][k] : mj[v] * inv[v][k]) * (inv[v][k] * inv[v][k]);
+          if (v & 1) {
+            bx[k] = fmaf(dx[v][k], sv, bx[k]);
+            by[k] = fmaf(dy[v][k], sv, by[k]);
+            bz[k] = fmaf(dz[v][k], sv, bz[k]);
+          } else {
+            ax[k] = fmaf(dx[v][k], sv, ax[k]);
+            ay[k] = fmaf(dy[v][k], sv, ay[k]);
+            az[k] = fmaf(dz[v][k], sv, az[k]);
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {  // full tile: constant trip count, two accumulator sets for ILP
+#pragma unroll 2
+    for (int u = u0; u < u0 + TW; u += 8) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        interact32<DS, K, MASK, POT, EQ>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
+                                         (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li,
+                                         j0 + u + v);
+    }
   }
 }
 
@@ -213,6 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     const PairItem item = a.items[it];
     const DevCluster c = a.cl[item.cluster];
     const double4 ref = a.ref[item.cluster];
+    const double mc = a.mconst[item.cluster];  // != 0: every mass of the cluster equals mc
+    const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
     float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K];
     float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K];
@@ -242,72 +314,24 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      store_tile<FAM, T>(a, sh, raw, ref);
+      store_tile<FAM, T>(a, sh, raw, ref, eq);
       __syncthreads();
       if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
-      if (PH && cnt == T) {  // full tile in rsq-grouped phases
-        constexpr int BJ = 8 / K;
-        for (int u = u0; u < u0 + TW; u += BJ) {
-          float dx[BJ][K], dy[BJ][K], dz[BJ][K], r2[BJ][K], inv[BJ][K], mj[BJ];
-#pragma unroll
-          for (int v = 0; v < BJ; ++v) {
-            const float4 pj = sh.hi[u + v];
-            const float4 pl = sh.lo_at(u + v);
-            mj[v] = pj.w;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              dx[v][k] = pj.x - xi[k];
-              dy[v][k] = pj.y - yi[k];
-              dz[v][k] = pj.z - zi[k];
-              if constexpr (DS) {
-                dx[v][k] += pl.x - xl[k];
-                dy[v][k] += pl.y - yl[k];
-                dz[v][k] += pl.z - zl[k];
-              }
-              float q = fmaf(dx[v][k], dx[v][k], e2);
-              q = fmaf(dy[v][k], dy[v][k], q);
-              r2[v][k] = fmaf(dz[v][k], dz[v][k], q);
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int v = 0; v < BJ; ++v)
-#pragma unroll
-            for (int k = 0; k < K; ++k) inv[v][k] = __builtin_amdgcn_rsqf(r2[v][k]);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int v = 0; v < BJ; ++v)
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              const float sv = (mj[v] * inv[v][k]) * (inv[v][k] * inv[v][k]);
-              if (v & 1) {
-                bx[k] = fmaf(dx[v][k], sv, bx[k]);
-                by[k] = fmaf(dy[v][k], sv, by[k]);
-                bz[k] = fmaf(dz[v][k], sv, bz[k]);
-              } else {
-                ax[k] = fmaf(dx[v][k], sv, ax[k]);
-                ay[k] = fmaf(dy[v][k], sv, ay[k]);
-                az[k] = fmaf(dz[v][k], sv, az[k]);
-              }
-            }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else if (cnt == T) {  // full tile: constant trip count, two accumulator sets for ILP
-#pragma unroll 2
-        for (int u = u0; u < u0 + TW; u += 8) {
-#pragma unroll
-          for (int v = 0; v < 8; ++v)
-            interact32<DS, K, MASK, POT>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
-                                         (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li, j0 + u + v);
-        }
-      } else {
+      if (cnt == T && eq)
+        full_tile_terms<FAM, K, TW, T, MASK, POT, PH, true>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx,
+                                                            by, bz, pt, li);
+      else if (cnt == T)
+        full_tile_terms<FAM, K, TW, T, MASK, POT, PH, false>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx,
+                                                             by, bz, pt, li);
+      else {  // partial tile: the stored weight (mass, or 1 / 0 for equal masses) zeroes the padding
         const int mine = min(TW, ((cnt - u0 + 7) & ~7));  // this wave's records, padded to 8
         for (int u = u0; u < u0 + mine; u += 8) {
 #pragma unroll
           for (int v = 0; v < 8; ++v)
-            interact32<DS, K, MASK, POT>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
-                                         (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li, j0 + u + v);
+            interact32<DS, K, MASK, POT, false>(sh.hi[u + v], sh.lo_at(u + v), xi, yi, zi, xl, yl, zl, e2,
+                                                (v & 1) ? bx : ax, (v & 1) ? by : ay, (v & 1) ? bz : az, pt, li,
+                                                j0 + u + v);
         }
       }
       if (FOLD) {
@@ -328,10 +352,26 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     if (!FOLD) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        Ax[k] = ax[k] + bx[k];
-        Ay[k] = ay[k] + by[k];
-        Az[k] = az[k] + bz[k];
-        Pt[k] = pt[k];
+        float sx = ax[k] + bx[k], sy = ay[k] + by[k], sz = az[k] + bz[k], sp = pt[k];
+        if (eq) {
+          const float mf = (float)mc;
+          sx *= mf;
+          sy *= mf;
+          sz *= mf;
+          sp *= mf;
+        }
+        Ax[k] = sx;
+        Ay[k] = sy;
+        Az[k] = sz;
+        Pt[k] = sp;
+      }
+    } else if (eq) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        Ax[k] *= mc;
+        Ay[k] *= mc;
+        Az[k] *= mc;
+        Pt[k] *= mc;
       }
     }
     reduce_and_finish<K, W, POT>(a, c, item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
@@ -340,6 +380,36 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
 
 // ---------------------------------------------------------------------------------------------
 // FP64 family
+
+// Pair terms of records [u0, u0 + cnt) of the LDS tile (cnt a multiple of 8), FP64 throughout;
+// EQ leaves the record weight out (all masses equal).
+template <int K, int T, bool MASK, bool POT, bool EQ>
+__device__ __forceinline__ void terms64(const PairLds<FAM_F64, T>& sh, int u0, int cnt, int j0, const double (&xi)[K],
+                                        const double (&yi)[K], const double (&zi)[K], double e2, double (&ax)[K],
+                                        double (&ay)[K], double (&az)[K], double (&pt)[K], const int (&li)[K]) {
+  for (int u = u0; u < u0 + cnt; u += 8) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double4 pj = sh.r[u + v];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double dx = pj.x - xi[k], dy = pj.y - yi[k], dz = pj.z - zi[k];
+        double r2 = fma(dx, dx, e2);
+        r2 = fma(dy, dy, r2);
+        r2 = fma(dz, dz, r2);
+        const double inv = rsqrt_f64(r2);
+        const double mi = EQ ? inv : pj.w * inv;
+        double s = mi * (inv * inv);
+        if (MASK) s = r2 > 0.0 ? s : 0.0;
+        ax[k] = fma(dx, s, ax[k]);
+        ay[k] = fma(dy, s, ay[k]);
+        az[k] = fma(dz, s, az[k]);
+        if (POT) pt[k] += (j0 + u + v != li[k]) ? mi : 0.0;
+      }
+    }
+  }
+}
+
 template <int K, int W, int T, bool MASK, bool POT>
 __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
   static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
@@ -352,6 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
     const PairItem item = a.items[it];
     const DevCluster c = a.cl[item.cluster];
+    const double mc = a.mconst[item.cluster];  // != 0: every mass of the cluster equals mc
+    const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
     double xi[K], yi[K], zi[K], ax[K], ay[K], az[K], pt[K];
     int li[K];
@@ -371,31 +443,23 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
-      store_tile<FAM_F64, T>(a, sh, raw, make_double4(0.0, 0.0, 0.0, 0.0));
+      store_tile<FAM_F64, T>(a, sh, raw, make_double4(0.0, 0.0, 0.0, 0.0), eq);
       __syncthreads();
       if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
-      const int mine = min(TW, ((cnt - u0 + 7) & ~7));
-      for (int u = u0; u < u0 + mine; u += 8) {
+      if (cnt == T && eq)
+        terms64<K, T, MASK, POT, true>(sh, u0, TW, j0, xi, yi, zi, e2, ax, ay, az, pt, li);
+      else  // the stored weight (mass, or 1 / 0 for equal masses) zeroes the padding
+        terms64<K, T, MASK, POT, false>(sh, u0, min(TW, ((cnt - u0 + 7) & ~7)), j0, xi, yi, zi, e2, ax, ay, az, pt,
+                                        li);
+    }
+    if (eq) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const double4 pj = sh.r[u + v];
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const double dx = pj.x - xi[k], dy = pj.y - yi[k], dz = pj.z - zi[k];
-            double r2 = fma(dx, dx, e2);
-            r2 = fma(dy, dy, r2);
-            r2 = fma(dz, dz, r2);
-            const double inv = rsqrt_f64(r2);
-            const double mi = pj.w * inv;
-            double s = mi * (inv * inv);
-            if (MASK) s = r2 > 0.0 ? s : 0.0;
-            ax[k] = fma(dx, s, ax[k]);
-            ay[k] = fma(dy, s, ay[k]);
-            az[k] = fma(dz, s, az[k]);
-            if (POT) pt[k] += (j0 + u + v != li[k]) ? mi : 0.0;
-          }
-        }
+      for (int k = 0; k < K; ++k) {
+        ax[k] *= mc;
+        ay[k] *= mc;
+        az[k] *= mc;
+        pt[k] *= mc;
       }
     }
     reduce_and_finish<K, W, POT>(a, c, item, ibase, ax, ay, az, pt, red, false, kick);

@@ -60,7 +60,7 @@ const Sym6 kSym6;
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, items, counters, coef, ref, partials, epart, pot, part, total;
+  size_t cl, chunks, items, counters, coef, ref, mconst, partials, epart, pot, part, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -194,8 +194,10 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + sizeof(double) * 3 * (size_t)B * kMaxRounds);
   L.ref = o;
   o = align_up(o + sizeof(double4) * B);
+  L.mconst = o;
+  o = align_up(o + sizeof(double) * B);
   L.partials = o;
-  o = align_up(o + sizeof(double4) * nchunks);
+  o = align_up(o + sizeof(double) * 5 * nchunks);
   L.epart = o;
   o = align_up(o + sizeof(double) * 16 * nchunks);
   L.pot = o;
@@ -335,7 +337,8 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.chunk_counter = reinterpret_cast<int*>(w + L.counters);
   a.item_counter = reinterpret_cast<int*>(w + L.counters) + p.B;
 
-  a.partials = reinterpret_cast<double4*>(w + L.partials);
+  a.partials = reinterpret_cast<double*>(w + L.partials);
+  a.mconst = reinterpret_cast<double*>(w + L.mconst);
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
   a.pot_ws = reinterpret_cast<double*>(w + L.pot);
@@ -385,7 +388,7 @@ int pair(nbody_ctx* ctx, const Prepared& P, bool potmode, bool kick, hipStream_t
 // counter) -> pair -> [combine of split clusters].
 int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, hipStream_t s) {
   hipError_t e;
-  e = launch_update(P.a, update, P.centred, s);  // also clears the pair kernel's work counter
+  e = launch_update(P.a, update, s);  // also clears the pair kernel's work counter
   if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
   int rc = pair(ctx, P, potmode, kick, s);
   if (rc || !ctx->plan.anysplit) return rc;
