@@ -212,6 +212,52 @@ def test_full_size_c3_sampled_rows():
         sim.close()
 
 
+def test_full_size_c2_sampled_rows_with_field():
+    """N = 65536 with Salpeter masses, eps = 1e-4 and the galaxy field (the sym6 workload): sampled
+    rows against the oracle (internal + field), with per-row scales."""
+    torch_dev()
+    b = inputs.c2()
+    rows = [(0, 64), (32768 - 32, 32768 + 32), (65536 - 64, 65536)]
+    for prec in ("fp64", "fp32ds", "fp32c"):
+        sim = make_sim(b, prec)
+        a = sim.accel().cpu().numpy()
+        errs = []
+        for r0, r1 in rows:
+            ref, absa = oracle.accel(b.pos, b.mass, 1.0, 1e-4, rows=(r0, r1), want_abs=True)
+            ae, _ = oracle.ext_field(b.pos[r0:r1], 1.0, b.galaxy)
+            errs.append(rel_errors(a[r0:r1], ref + ae, absa + np.linalg.norm(ae, axis=1)))
+        err = np.concatenate(errs)
+        print("\n[C2 %s sampled] %s" % (prec, stats(err)), flush=True)
+        if prec in TOL:
+            assert err.max() <= TOL[prec]
+        assert np.median(err) <= TOL_MEDIAN[prec]
+        sim.close()
+
+
+def test_full_size_c4_sampled_clusters():
+    """The 512-cluster ensemble in one launch: the smallest, the largest and clusters of each split
+    class checked whole against the oracle."""
+    torch_dev()
+    b = inputs.c4()
+    sizes = np.diff(b.offsets)
+    order = np.argsort(sizes)
+    pick = sorted(set([int(order[0]), int(order[-1])] + [int(order[np.searchsorted(sizes[order], n)])
+                                                         for n in (1024, 2048, 4096, 9000)]))
+    for prec in ("fp32ds", "fp64"):
+        sim = make_sim(b, prec)
+        a = sim.accel().cpu().numpy()
+        errs = []
+        for c in pick:
+            s, e = b.offsets[c], b.offsets[c + 1]
+            ref, _, absa = oracle.accel(b.pos[s:e], b.mass[s:e], 1.0, 1e-3, want_pot=True, want_abs=True)
+            errs.append(rel_errors(a[s:e], ref, absa))
+        err = np.concatenate(errs)
+        print("\n[C4 %s clusters %s] %s" % (prec, [int(sizes[c]) for c in pick], stats(err)), flush=True)
+        assert err.max() <= TOL[prec]
+        assert np.median(err) <= TOL_MEDIAN[prec]
+        sim.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32ds", "fp32c"])
 @pytest.mark.parametrize("tile", [(2, 4, 256, 4, 1), (1, 4, 256, 8, 1), (2, 2, 256, 4, 1), (2, 4, 128, 8, 1),
                                   (1, 1, 128, 2, 0), (1, 2, 256, 8, 0)])
@@ -235,3 +281,32 @@ def test_launch_shapes_agree(prec, tile):
         for ncl in range(3):
             nbody.nbody_set_tile(sim.ctx, prec, ncl, *tile[:4], 0)
         assert np.array_equal(sim.accel().cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c"])
+def test_equal_and_nearly_equal_masses(prec):
+    """Clusters whose masses are all equal take the path that scales the mass-free sums by the
+    common mass once; one different mass anywhere (first particle, last chunk, a split cluster)
+    must take the weighted path.  Both match the oracle, potential included."""
+    torch_dev()
+    cl = []
+    for c, (n, odd) in enumerate(((700, None), (1300, -1), (1300, 0), (3000, None), (3000, 2999), (5, None))):
+        p, v, m = inputs.plummer(n, 4400 + c)
+        m = m.copy()
+        if odd is not None:
+            m[odd] *= 1.5
+        cl.append(inputs.single(p, v, m, 1e-3 if c != 5 else 0.0, False))
+    b = inputs.concat(cl)
+    sim = make_sim(b, prec)
+    a = sim.accel(pot=True).cpu().numpy()
+    pot = sim.pot.cpu().numpy()
+    ref, scale, rpot = oracle_reference(b, want_pot=True)
+    err = rel_errors(a, ref, scale)
+    print("\n[masses %s] %s" % (prec, stats(err)), flush=True)
+    if prec in TOL:
+        assert err.max() <= TOL[prec]
+    assert np.median(err) <= TOL_MEDIAN[prec]
+    ptol = {"fp64": 1e-13, "fp32ds": 2e-6, "fp32c": 1e-5}[prec]
+    for c in range(b.B):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        assert np.abs(pot[s:e] - rpot[s:e]).max() <= ptol * np.abs(rpot[s:e]).max(), c
