@@ -64,6 +64,9 @@ def workload(name):
     return inputs.c4(), "fp32ds"
 
 
+ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
+
+
 def traffic_from_profile(prec, tile=None):
     """HBM bytes per pair-kernel launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE calibrated against a plain copy), or None if the kernel source or the launch shape
@@ -162,7 +165,8 @@ def cpu_baseline(batch, pos_all, target_s, a_gpu):
     oracle.build()
     n = int(batch.offsets[1])
     pos, mass, eps = pos_all[:n], batch.mass[:n], float(batch.eps[0])
-    probe = max(1, min(n, 16))
+    probe = max(1, min(n, 256))
+    oracle.accel(pos, mass, batch.G, eps, rows=(0, probe))  # starts the thread pool
     t0 = time.perf_counter()
     oracle.accel(pos, mass, batch.G, eps, rows=(0, probe))
     tp = max(time.perf_counter() - t0, 1e-6)
@@ -184,6 +188,25 @@ def cpu_baseline(batch, pos_all, target_s, a_gpu):
         "sample": "rows [0,%d) of the first cluster (N=%d) against all its sources, one FP64 force evaluation, "
                   "%.1f s" % (rows, n, el),
     }, {"rows": rows, "max": float(err.max()), "median": float(np.median(err))}
+
+
+def mode_errors(batch, accel_init, nrows):
+    """Error of every precision mode's first force evaluation against the oracle on the first nrows
+    particles of the first cluster (initial state): err_i = |a_i - a_ref,i| / S_i as in the tests."""
+    import numpy as np
+    import oracle
+    n = int(batch.offsets[1])
+    ref, absa = oracle.accel(batch.pos[:n], batch.mass[:n], batch.G, float(batch.eps[0]), rows=(0, nrows),
+                             want_abs=True)
+    if batch.field[0]:
+        ae, _ = oracle.ext_field(batch.pos[:nrows], batch.G, batch.galaxy)
+        ref = ref + ae
+        absa = absa + np.linalg.norm(ae, axis=1)
+    out = {}
+    for m, a in accel_init.items():
+        err = np.linalg.norm(a - ref, axis=1) / absa
+        out[m] = {"rows": nrows, "max": float(err.max()), "median": float(np.median(err))}
+    return out
 
 
 def serve_requests(jobs):
@@ -288,6 +311,8 @@ def main():
     from paper_1003_3896_amd import autotune
     tile_used = nbody.nbody_get_tile(sim.ctx, prec, autotune.size_class(int(np.diff(batch.offsets).max())))
     e_start = energy_fp64(sim) if args.workload in ("c1", "c2", "c3") else None
+    nrows = min(int(batch.offsets[1]), ACCEL_ROWS)
+    accel_init = {prec: sim.accel().cpu().numpy()[:nrows].copy()}  # initial state, for the error table
     wall, kms, nlaunch = time_steps(sim, integrator, dt, args.steps, args.warmup, torch)
     e_end = energy_fp64(sim) if e_start is not None else None
     inter = inter_per_eval * evals_per_step * args.steps
@@ -303,7 +328,7 @@ def main():
         "frac": round(achieved / fam_peak, 4),
         "traffic": traffic_from_profile(prec, tile_used),
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
-                 "blocks_per_cu": tile_used[3]},
+                 "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
         "kernel": "pair (%s)" % prec,
         "kernel_ms": round(pair_ms, 4),
         "launches": nlaunch,
@@ -320,12 +345,12 @@ def main():
             if m == prec:
                 continue
             s2 = nbody.Simulation(batch, m)
-            st = max(2, args.steps // 6)
             a0 = energy_fp64(s2)
-            w2, k2, n2 = time_steps(s2, integrator, dt, st, 1, torch)
-            modes[m] = {"G_interactions_per_s": round(inter_per_eval * evals_per_step * st / w2 / 1e9, 2),
+            accel_init[m] = s2.accel().cpu().numpy()[:nrows].copy()
+            w2, k2, n2 = time_steps(s2, integrator, dt, args.steps, args.warmup, torch)
+            modes[m] = {"G_interactions_per_s": round(inter_per_eval * evals_per_step * args.steps / w2 / 1e9, 2),
                         "pair_kernel_ms": round(k2 / max(n2, 1), 4),
-                        "energy": dict(drift_report(a0, energy_fp64(s2)), steps=st + 1)}
+                        "energy": dict(drift_report(a0, energy_fp64(s2)), steps=args.steps + args.warmup)}
             s2.close()
 
     result = {
@@ -384,6 +409,7 @@ def main():
         cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
         result["cpu_baseline"] = cb
         result["parity_sample"] = parity
+        result["accel_error_initial_state"] = mode_errors(batch, accel_init, nrows)
     print(json.dumps(result), flush=True)
 
 
