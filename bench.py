@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--jobs", type=int, default=120, help="c5: jobs in the open-loop stream")
     ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
+    ap.add_argument("--policy", default="srpt", choices=["srpt", "all"], help="c5: which active jobs a round advances")
+    ap.add_argument("--fill", type=float, default=2.0 ** 28, help="c5: pair interactions a round gathers (srpt)")
     ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
@@ -67,11 +69,16 @@ def workload(name):
 ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
 
 
-def traffic_from_profile(prec, tile=None):
-    """HBM bytes per pair-kernel launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE calibrated against a plain copy), or None if the kernel source or the launch shape
-    has changed since the counters were taken or no summary exists for this mode."""
-    path = os.path.join(ROOT, "profiles", "pair_%s_plummer262144.md" % prec)
+PROFILE_TAG = {"c3": "plummer262144"}  # workloads with a committed counter summary
+
+
+def traffic_from_profile(prec, tile=None, workload="c3"):
+    """HBM bytes per pair-kernel launch from the committed counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE calibrated against a plain copy), or None if the kernel source or
+    the launch shape has changed since the counters were taken or no summary exists."""
+    if workload not in PROFILE_TAG:
+        return None
+    path = os.path.join(ROOT, "profiles", "pair_%s_%s.md" % (prec, PROFILE_TAG[workload]))
     src = os.path.join(ROOT, "paper_1003_3896_amd", "csrc", "pair_kernel.h")
     if not os.path.exists(path):
         return None
@@ -231,18 +238,21 @@ def bench_c5(args):
     sat = serve_requests(inputs.c5_jobs(args.sat_jobs, 0.0, seed=5006))
     for r in sat:
         r.arrival = 0.0
-    srv = Server(ex, energy=False)
+    srv = Server(ex, energy=False, policy=args.policy, fill=args.fill)
     t0 = time.perf_counter()
     res = srv.run(sat)
     el = time.perf_counter() - t0
     work = sum(r.interactions() for r in sat if res[r.jid].status == "done")
     xsat = work / el
     print("c5: saturation %.3e int/s over %d jobs in %.1f s" % (xsat, len(sat), el), file=sys.stderr, flush=True)
-    mean_work = 5.16e8 * 505 * 4  # E[N^2] E[steps] E[evals/step] of the job distribution
+    # the stream's sizes and step counts do not depend on the rate: take its own mean work, so the
+    # offered load is the stated fraction of the measured saturation throughput
+    probe = inputs.c5_jobs(args.jobs, 1.0)
+    mean_work = sum(j.n * j.n * j.steps * (1 if j.integrator == "leapfrog" else 7) for j in probe) / len(probe)
     rate = args.load * xsat / mean_work
     jobs = inputs.c5_jobs(args.jobs, rate)
     reqs = serve_requests(jobs)
-    srv = Server(ex, energy=True)
+    srv = Server(ex, energy=True, policy=args.policy, fill=args.fill)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     el = time.perf_counter() - t0
@@ -251,6 +261,8 @@ def bench_c5(args):
     warm = max(1, args.jobs // 20)
     lat = latency_stats(res, skip=warm)
     dE = [res[r.jid].rel_energy_error for r in done]
+    # stretch: latency over the job's own work at the saturation rate
+    stretch = sorted(res[r.jid].latency / (r.interactions() / xsat) for r in done if r.jid >= warm)
     ex.close()
     return {
         "metric": METRIC,
@@ -268,9 +280,12 @@ def bench_c5(args):
         "config": {"workload": "served stream: N log-uniform [1024,65536], steps U[10,1000], leapfrog/sym6 "
                                "50/50, galaxy field on half, eps=1e-3, dt=2^-11, fp32ds",
                    "jobs": args.jobs, "offered_load": args.load, "arrival_rate_per_s": round(rate, 4),
-                   "arena_particles": cap, "max_clusters": maxb},
+                   "arena_particles": cap, "max_clusters": maxb, "policy": args.policy,
+                   "fill": args.fill},
         "latency_s": {"p50": round(lat["p50"], 4), "p99": round(lat["p99"], 4), "mean": round(lat.get("mean", 0), 4),
                       "jobs_counted": lat["n"]},
+        "stretch": {"p50": round(float(np.percentile(stretch, 50)), 3),
+                    "p99": round(float(np.percentile(stretch, 99)), 3)} if stretch else None,
         "saturation_G_interactions_per_s": round(xsat / 1e9, 3),
         "rounds": srv.rounds,
         "jobs_done": len(done),
@@ -326,7 +341,7 @@ def main():
         "peak": fam_peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / fam_peak, 4),
-        "traffic": traffic_from_profile(prec, tile_used),
+        "traffic": traffic_from_profile(prec, tile_used, args.workload),
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
                  "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
         "kernel": "pair (%s)" % prec,
@@ -391,7 +406,7 @@ def main():
             s3 = nbody.Simulation(batch, prec)
             nbody.nbody_use_graphs(s3.ctx, use)
             s3.accel()
-            s3.step(integrator, dt, 2)
+            s3.step(integrator, dt, args.steps)  # the same call as the timed one: graphs captured here
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s3.step(integrator, dt, args.steps)

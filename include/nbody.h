@@ -98,8 +98,8 @@ void nbody_destroy(nbody_ctx* ctx);
 /* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
  * nbody_last_error() says why): 8 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
- * about 2^17/N ranges, a power of two of at most 8 with at least 512 sources each, so clusters of
- * 1024..131071 particles are split), plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned; its contents
+ * about 2^17/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
+ * 512..65536 particles are split), plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned; its contents
  * are the library's between calls (the caller must not modify it while calls using it are in
  * flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);
@@ -190,11 +190,13 @@ typedef struct {
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);
 
-/* Step graphs (enable = 1, the default): nbody_step_leapfrog / nbody_step_sym6 calls with
- * nsteps >= 2 capture the kernels of one step into a HIP graph (once per argument set; a change of
- * any pointer, dt, system layout or launch shape recaptures) and replay it nsteps times on a
- * context-owned stream ordered after, and before, the caller's stream.  Results are bitwise those of
- * the direct launches.  Disabled automatically while per-kernel timing is on. */
+/* Step graphs (enable = 1; off by default, because replaying captured steps has measured slower
+ * than launching the same kernels directly on gfx950 under ROCm 7).  When on, nbody_step_leapfrog /
+ * nbody_step_sym6 calls with nsteps >= 2 capture the kernels of up to 8 steps into a HIP graph, and
+ * nbody_substeps calls with nrounds >= 2 capture their rounds, once per argument set (a change of
+ * any pointer, dt, system layout or launch shape recaptures; 8 graphs are cached), and replay them
+ * on a context-owned stream ordered after, and before, the caller's stream.  Results are bitwise
+ * those of the direct launches.  Disabled automatically while per-kernel timing is on. */
 int nbody_use_graphs(nbody_ctx* ctx, int enable);
 
 /* Per-kernel timing with HIP events recorded on the call's stream around every pair-kernel

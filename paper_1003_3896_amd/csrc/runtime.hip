@@ -84,11 +84,17 @@ struct Slot {
 };
 
 // j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
-// on their own (about 2^17 / N ranges, a power of two, at most 8), each range at least 512 sources.
+// on their own (about 2^17 / N ranges, a power of two, at most 8), each range at least 256 sources.
 // Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
+#ifndef NB_MIN_RANGE
+#define NB_MIN_RANGE 256  // fewest sources in one j-range of a split cluster (a tuning constant)
+#endif
+#ifndef NB_SPLIT_CAP
+#define NB_SPLIT_CAP (1LL << 17)  // bound on N x ranges (partial sums kept per cluster)
+#endif
 int split_of(int n) {
   int s = 1;
-  while (s < 8 && (long long)n * (2 * s) <= (1 << 17) && n / (2 * s) >= 512) s *= 2;
+  while (s < 8 && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
   return s;
 }
 
@@ -108,7 +114,7 @@ struct StepGraph {
 struct nbody_ctx {
   int device = 0;
   int cus = 256;
-  bool graphs = true;
+  bool graphs = false;
   hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<StepGraph> gcache;  // small LRU cache of captured graphs (most recent last)
@@ -647,7 +653,7 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   // sum split_c n_c <= min(8 n, B 2^17) (split_c n_c <= 2^17 whenever split_c > 1)
   const long long nchunks = B + n / kChunk;
   const long long nitems = 8 * (B + n / 64);
-  const long long npart = std::min(8 * n, B * (1LL << 17));
+  const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
   return make_layout((int)B, n, (int)nchunks, nitems, npart).total;
 }
 

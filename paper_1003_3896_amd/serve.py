@@ -2,19 +2,21 @@
 
 Jobs (one isolated cluster each: initial state, integrator, number of steps, softening, field
 flag) arrive over time.  The server keeps every admitted job's state on the device in one
-particle arena, concatenated in admission order, and advances ALL active jobs together: each
-round is one ``nbody_substep`` call over the ragged batch of active jobs, every job at its own
-integrator stage (its own kick/drift coefficients).  A job's first round is an evaluation-only
-substep (all coefficients 0) that produces its first acceleration; after that a leapfrog step is
-one substep (dt/2, dt, dt/2) and a 6th-order step is seven (the composition's merged kicks and
-drifts, taken from the library).  Jobs that arrive while others run are admitted as soon as arena
-space and cluster slots allow (admission by bytes of device memory), so their work overlaps on
-the device with the jobs already running; finished jobs are retired, their energy evaluated, and
-the arena compacted.
+particle arena and advances the jobs in rounds: each round is one stage of the ragged batch of
+jobs at the front of the arena, every job at its own integrator stage (its own kick/drift
+coefficients), and up to 64 rounds go to the device in one ``nbody_substeps`` call.  A job's
+first round is an evaluation-only substep (all coefficients 0) that produces its first
+acceleration; after that a leapfrog step is one substep (dt/2, dt, dt/2) and a 6th-order step is
+seven (the composition's merged kicks and drifts, taken from the library).  Jobs that arrive while
+others run are admitted as soon as arena space and cluster slots allow (admission by bytes of
+device memory), so their work overlaps on the device with the jobs already running.  By default
+the arena is kept in order of remaining work and a round takes the leading jobs until it holds
+enough pair interactions to occupy the device, so short jobs finish at their own pace; finished
+jobs are retired, their energy evaluated, and the arena compacted.
 
 Because each cluster's arithmetic depends only on its own data and on the pair kernel's fold
-pattern (pinned here to one tile shape for every cluster size), a job's result is bitwise the same
-whether it ran alone or in a mix.
+pattern (the same tile length and waves per i-group for every cluster size here), a job's result is
+bitwise the same whether it ran alone or in a mix.
 
 The device work goes through an executor; ``HipExecutor`` is the GPU one.  Tests drive the same
 control logic with a CPU stand-in.
@@ -31,6 +33,7 @@ import numpy as np
 from . import nbody
 
 STATE_BYTES_PER_PARTICLE = 80  # pos 24 + vel 24 + acc 24 + mass 8 (float64)
+SERVE_TILE = (256, 2)          # (j-records per LDS tile, waves per i-group) for every served job
 
 
 @dataclass
@@ -108,9 +111,14 @@ class HipExecutor:
     """Device side of the server: a particle arena, its workspace and the library context."""
 
     def __init__(self, capacity: int, max_clusters: int, prec: str = "fp32ds", device: int = 0,
-                 energy_prec: str = "fp64", tile=(1, 4, 128, 8, 0), G: float = 1.0, galaxy=None):
+                 energy_prec: str = "fp64", tile=None, G: float = 1.0, galaxy=None, max_inflight: int = 2):
+        import collections
         import torch
         self.torch = torch
+        # calls whose device work may still be queued: bounding them bounds how long a newly admitted
+        # job waits behind work enqueued for the jobs already running
+        self.max_inflight = int(max_inflight)
+        self._inflight = collections.deque()
         self.dev = torch.device("cuda", device)
         self.capacity = int(capacity)
         self.max_clusters = int(max_clusters)
@@ -119,10 +127,16 @@ class HipExecutor:
         self.G = G
         self.galaxy = tuple(galaxy) if galaxy is not None else nbody.System([0, 1], [0.0]).galaxy
         self.ctx = nbody.nbody_create(device)
-        # one launch shape for every size class: results independent of the batch composition
-        for p in {prec, energy_prec}:
-            for ncl in range(3):
-                nbody.nbody_set_tile(self.ctx, p, ncl, *tile)
+        # Results depend on the tile length and the waves per group (the fold pattern), not on the
+        # i-particles per lane, blocks per CU or the phased loop: every size class gets the same
+        # (tile, waves) and its own tuned rest, so a job's result does not depend on the batch.
+        if tile is None:
+            from . import autotune
+            autotune.apply(self.ctx, fixed_tile={fam: SERVE_TILE for fam in ("f32", "ds", "f64")})
+        else:
+            for p in {prec, energy_prec}:
+                for ncl in range(3):
+                    nbody.nbody_set_tile(self.ctx, p, ncl, *tile)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.pos = torch.zeros(self.capacity, 3, **f64)
         self.vel = torch.zeros(self.capacity, 3, **f64)
@@ -166,6 +180,11 @@ class HipExecutor:
         sys = self._system(sizes, eps, fld, self.prec)
         nbody.nbody_substeps(self.ctx, sys, self.pos, self.vel, self.mass, self.acc, coef, self.ws_addr,
                              self.ws_bytes)
+        ev = self.torch.cuda.Event()
+        ev.record()
+        self._inflight.append(ev)
+        while len(self._inflight) > self.max_inflight:
+            self._inflight.popleft().synchronize()
 
     def energy(self, offset: int, sizes, eps, fld) -> np.ndarray:
         """Diagnostics of the consecutive jobs starting at ``offset`` (one row each)."""
@@ -175,6 +194,15 @@ class HipExecutor:
         nbody.nbody_energy(self.ctx, sys, self.pos.data_ptr() + 24 * o, self.vel.data_ptr() + 24 * o,
                            self.mass.data_ptr() + 8 * o, self.eout.data_ptr(), self.ws_addr, self.ws_bytes)
         return self.eout[:B].cpu().numpy().copy()
+
+    def reorder(self, spans) -> None:
+        """Rewrite the arena from offset 0 as the concatenation of the (offset, n) spans, in order."""
+        t = self.torch
+        idx = np.concatenate([np.arange(o, o + n, dtype=np.int64) for o, n in spans])
+        it = t.from_numpy(idx).to(self.dev)
+        m = idx.shape[0]
+        for buf in (self.pos, self.vel, self.acc, self.mass):
+            buf[:m] = buf.index_select(0, it)
 
     def move(self, src: int, dst: int, n: int) -> None:
         """Move n particles of state from src to dst < src (compaction)."""
@@ -189,6 +217,7 @@ class HipExecutor:
 
     def sync(self) -> None:
         self.torch.cuda.synchronize()
+        self._inflight.clear()
 
 
 class Server:
@@ -196,8 +225,17 @@ class Server:
     executor).  ``run(requests)`` replays arrival times against the wall clock."""
 
     def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None, round_budget_s: float = 4e-3,
-                 rate_estimate: float = 2e12, max_rounds_per_call: int = 64):
+                 rate_estimate: float = 2e12, max_rounds_per_call: int = 64, policy: str = "srpt",
+                 fill: float = 2.0 ** 28):
+        if policy not in ("srpt", "all"):
+            raise ValueError("policy must be 'srpt' or 'all'")
         self.ex = executor
+        # "all": every active job advances every round.  "srpt": the arena is kept in order of
+        # remaining work (least first) and the rounds advance the leading jobs only, as many as it
+        # takes for a round to hold `fill` pair interactions (enough work to occupy the device), so
+        # short jobs are not held to the round rate of the largest ones.
+        self.policy = policy
+        self.fill = float(fill)
         self.energy = energy
         self.clock = clock
         # rounds are chained in one call while no job starts or ends, up to about round_budget_s of
@@ -250,18 +288,49 @@ class Server:
                                [a.req.field for a in new])
             for a, row in zip(new, e):
                 a.energy0 = row
+        if new and self.policy == "srpt":
+            self._reorder()
         return new
 
+    @staticmethod
+    def remaining(a: _Active) -> int:
+        """Pair interactions a job still needs."""
+        return a.left * a.req.n * a.req.n
+
+    def _reorder(self) -> None:
+        """Rearrange the arena in order of remaining work (ties: arrival, then id)."""
+        order = sorted(self.active, key=lambda a: (self.remaining(a), a.req.arrival, a.req.jid))
+        if all(x is y for x, y in zip(order, self.active)):
+            return
+        self.ex.reorder([(a.offset, a.req.n) for a in order])
+        off = 0
+        for a in order:
+            a.offset = off
+            off += a.req.n
+        self.active = order
+
+    def batch(self) -> List[_Active]:
+        """The jobs the next rounds advance: a prefix of the arena (see ``policy``)."""
+        if self.policy == "all":
+            return self.active
+        tot = 0
+        for i, a in enumerate(self.active):
+            tot += a.req.n * a.req.n
+            if tot >= self.fill:
+                return self.active[:i + 1]
+        return self.active
+
     # -- rounds --------------------------------------------------------------------------
-    def chain_length(self) -> int:
-        """Rounds to run in one call: until the first active job finishes, within the budget."""
-        acts = self.active
+    def chain_length(self, acts: Optional[List[_Active]] = None) -> int:
+        """Rounds to run in one call: until the first job of the batch finishes, within the budget."""
+        acts = self.active if acts is None else acts
         per_round = sum(a.req.n * a.req.n for a in acts) / self.rate_estimate
         budget = max(1, int(self.round_budget_s / max(per_round, 1e-12)))
         return max(1, min(min(a.left for a in acts), budget, self.max_rounds_per_call))
 
-    def step_rounds(self, rounds: int = 1) -> None:
-        acts = self.active
+    def step_rounds(self, rounds: int = 1, acts: Optional[List[_Active]] = None) -> None:
+        """``rounds`` rounds over the jobs ``acts`` (default: all active), a prefix of the arena."""
+        acts = self.active if acts is None else acts
         coef = np.stack([a.schedule[a.cursor:a.cursor + rounds] for a in acts], axis=1)  # [R][B][3]
         self.ex.substeps([a.req.n for a in acts], [a.req.eps for a in acts], [a.req.field for a in acts], coef)
         self.rounds += rounds
@@ -320,11 +389,12 @@ class Server:
                     r = self.queue.pop(0)
                     self.results[r.jid] = Result(r.jid, "rejected", reason="does not fit")
                 continue
-            nr = self.chain_length()
+            acts = self.batch()
+            nr = self.chain_length(acts)
             if max_rounds is not None:
                 nr = max(1, min(nr, max_rounds - self.rounds))
-            self.step_rounds(nr)
-            if any(a.left == 0 for a in self.active) or self.cancelled:
+            self.step_rounds(nr, acts)
+            if any(a.left == 0 for a in acts) or self.cancelled:
                 self.ex.sync()
                 self._retire(now_fn)
             if max_rounds is not None and self.rounds >= max_rounds:

@@ -49,6 +49,12 @@ class FakeExecutor:
             o += n
         return np.array(out)
 
+    def reorder(self, spans):
+        self.reorders = getattr(self, "reorders", 0) + 1
+        idx = np.concatenate([np.arange(o, o + n) for o, n in spans])
+        for b in (self.pos, self.vel, self.acc, self.mass):
+            b[:len(idx)] = b[idx]
+
     def move(self, src, dst, n):
         for b in (self.pos, self.vel, self.acc, self.mass):
             b[dst:dst + n] = b[src:src + n].copy()

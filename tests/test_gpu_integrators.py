@@ -30,6 +30,7 @@ def test_substeps_equal_repeated_substep(prec):
     rng = np.random.default_rng(5)
     s1 = nbody.Simulation(b, prec)
     s2 = nbody.Simulation(b, prec)
+    nbody.nbody_use_graphs(s1.ctx, True)
     s1.accel()
     s2.accel()
     for call in range(3):

@@ -96,3 +96,46 @@ def test_arrivals_and_latency_stats():
     st = latency_stats(res)
     assert st["n"] == 6 and 0 < st["p50"] <= st["p99"]
     assert all(res[j].latency > 0 for j in range(6))
+
+
+def test_short_job_overtakes_long_one():
+    """Least-remaining-work order: a short job that arrives while a long one runs goes to the front
+    of the arena and, with a fill of one cluster, runs alone until it is done."""
+    t = [0.0]
+
+    def clock():
+        t[0] += 0.001
+        return t[0]
+
+    long_job = _req(0, 40, 30, "leapfrog")
+    short = _req(1, 20, 2, "leapfrog", arrival=0.004)
+    ex = FakeExecutor(capacity=100, max_clusters=4)
+    srv = Server(ex, clock=clock, sym6=SYM6, fill=1.0, max_rounds_per_call=1)
+    res = srv.run([long_job, short])
+    assert res[1].latency < res[0].latency
+    assert ex.reorders >= 1
+    # after the short job's admission, every round until it finished advanced it alone
+    i = next(k for k, c in enumerate(ex.calls) if c == [20])
+    assert ex.calls[i:i + 3] == [[20]] * 3
+    for r in (long_job, short):
+        p, v, _ = _solo_oracle(r)
+        assert np.array_equal(res[r.jid].pos, p) and np.array_equal(res[r.jid].vel, v)
+
+
+@pytest.mark.parametrize("policy,fill", [("all", 1.0), ("srpt", 1.0), ("srpt", 2000.0)])
+def test_policies_give_solo_results(policy, fill):
+    reqs = [_req(0, 40, 3, "leapfrog", arrival=0.0), _req(1, 25, 2, "sym6", True, arrival=0.0),
+            _req(2, 30, 1, "leapfrog", arrival=0.0)]
+    ex = FakeExecutor(capacity=200, max_clusters=4)
+    res = Server(ex, sym6=SYM6, policy=policy, fill=fill).run(reqs)
+    for r in reqs:
+        p, v, _ = _solo_oracle(r)
+        assert np.array_equal(res[r.jid].pos, p) and np.array_equal(res[r.jid].vel, v), (policy, r.jid)
+    if policy == "all":
+        assert ex.calls[0] == [40, 25, 30]
+    elif fill == 1.0:
+        assert all(len(c) == 1 for c in ex.calls)  # one job per round
+    else:
+        assert max(len(c) for c in ex.calls) >= 2  # 30^2 + 25^2 < 2000 <= + 40^2: up to three
+    with pytest.raises(ValueError):
+        Server(ex, policy="fifo")
