@@ -70,6 +70,16 @@ ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
 
 
 PROFILE_TAG = {"c3": "plummer262144"}  # workloads with a committed counter summary
+# sources that decide what a pair-kernel launch does (its code, work items and split rule)
+PAIR_SOURCES = [os.path.join(ROOT, "paper_1003_3896_amd", "csrc", f)
+                for f in ("pair_kernel.h", "nb_device.h", "nb_internal.h", "runtime.hip")]
+
+
+def pair_source_hash():
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(prec, tile=None, workload="c3"):
@@ -79,15 +89,16 @@ def traffic_from_profile(prec, tile=None, workload="c3"):
     if workload not in PROFILE_TAG:
         return None
     path = os.path.join(ROOT, "profiles", "pair_%s_%s.md" % (prec, PROFILE_TAG[workload]))
-    src = os.path.join(ROOT, "paper_1003_3896_amd", "csrc", "pair_kernel.h")
+    src = PAIR_SOURCES
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
-            fields[k.strip()] = v.strip().strip("`")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            v = v.split()
+            fields[k.strip()] = v[0].strip("`") if v else ""
+    h = pair_source_hash()
     if fields.get("kernel_source_sha256") != h:
         return None
     if tile is not None and fields.get("tile") != ",".join(str(v) for v in tile):

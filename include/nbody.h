@@ -98,8 +98,8 @@ void nbody_destroy(nbody_ctx* ctx);
 /* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
  * nbody_last_error() says why): 8 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
- * about 2^17/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
- * 512..65536 particles are split), plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned; its contents
+ * about 2^19/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
+ * 512..131071 particles are split), plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned; its contents
  * are the library's between calls (the caller must not modify it while calls using it are in
  * flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);

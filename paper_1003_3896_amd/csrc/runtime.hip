@@ -84,16 +84,21 @@ struct Slot {
 };
 
 // j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
-// on their own (about 2^17 / N ranges, a power of two, at most 8), each range at least 256 sources.
+// on their own (about 2^19 / N ranges, a power of two, at most 8), each range at least 256 sources;
+// clusters of 2^17 particles or more are not split.
 // Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
 #ifndef NB_MIN_RANGE
 #define NB_MIN_RANGE 256  // fewest sources in one j-range of a split cluster (a tuning constant)
 #endif
 #ifndef NB_SPLIT_CAP
-#define NB_SPLIT_CAP (1LL << 17)  // bound on N x ranges (partial sums kept per cluster)
+#define NB_SPLIT_CAP (1LL << 19)  // bound on N x ranges (partial sums kept per cluster)
+#endif
+#ifndef NB_SPLIT_BELOW
+#define NB_SPLIT_BELOW (1 << 17)  // from this size on, a cluster's i-tiles alone fill the chip
 #endif
 int split_of(int n) {
   int s = 1;
+  if (n >= NB_SPLIT_BELOW) return 1;
   while (s < 8 && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
   return s;
 }
@@ -650,7 +655,7 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   }
   const long long n = max_particles, B = max_clusters;
   // sum ceil(n_c/256) <= B + n/256; sum ceil(n_c/64) split_c <= 8 (B + n/64);
-  // sum split_c n_c <= min(8 n, B 2^17) (split_c n_c <= 2^17 whenever split_c > 1)
+  // sum split_c n_c <= min(8 n, B NB_SPLIT_CAP) (split_c n_c <= NB_SPLIT_CAP whenever split_c > 1)
   const long long nchunks = B + n / kChunk;
   const long long nitems = 8 * (B + n / 64);
   const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
