@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
     ap.add_argument("--policy", default="srpt", choices=["srpt", "all"], help="c5: which active jobs a round advances")
-    ap.add_argument("--fill", type=float, default=2.0 ** 28, help="c5: pair interactions a round gathers (srpt)")
+    ap.add_argument("--fill", type=float, default=2.0 ** 30, help="c5: pair interactions a round gathers (srpt)")
     ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")

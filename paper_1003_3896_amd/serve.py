@@ -226,7 +226,7 @@ class Server:
 
     def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None, round_budget_s: float = 4e-3,
                  rate_estimate: float = 2e12, max_rounds_per_call: int = 64, policy: str = "srpt",
-                 fill: float = 2.0 ** 28):
+                 fill: float = 2.0 ** 30):
         if policy not in ("srpt", "all"):
             raise ValueError("policy must be 'srpt' or 'all'")
         self.ex = executor
@@ -271,12 +271,24 @@ class Server:
         self.cancelled.add(jid)
 
     def _admit(self, now: float) -> List[_Active]:
+        """Admit queued jobs while they fit: in arrival order, stopping at the first that does not
+        fit ("all"), or least work first, skipping those that do not fit yet ("srpt")."""
         new = []
-        while self.queue and self.fits(self.queue[0]):
-            req = self.queue.pop(0)
+        if self.policy == "srpt":
+            self.queue.sort(key=lambda r: (r.interactions(), r.arrival, r.jid))
+        i = 0
+        while i < len(self.queue):
+            req = self.queue[i]
             if req.jid in self.cancelled:
+                self.queue.pop(i)
                 self.results[req.jid] = Result(req.jid, "cancelled")
                 continue
+            if not self.fits(req):
+                if self.policy == "srpt":
+                    i += 1
+                    continue
+                break
+            self.queue.pop(i)
             off = self.used()
             self.ex.load(off, req)
             sched = np.array(stage_schedule(req.integrator, req.dt, req.steps, self.sym6), dtype=np.float64)

@@ -139,3 +139,25 @@ def test_policies_give_solo_results(policy, fill):
         assert max(len(c) for c in ex.calls) >= 2  # 30^2 + 25^2 < 2000 <= + 40^2: up to three
     with pytest.raises(ValueError):
         Server(ex, policy="fifo")
+
+
+def test_queue_admits_small_job_past_a_big_one():
+    """A queued job too big for the free arena space does not hold back a smaller one behind it
+    (least-work admission); in arrival order ("all") it does."""
+    for policy, small_first in (("srpt", True), ("all", False)):
+        running = _req(0, 60, 6, "leapfrog", arrival=0.0)
+        big = _req(1, 60, 1, "leapfrog", arrival=0.0)
+        small = _req(2, 30, 1, "leapfrog", arrival=0.0)
+        ex = FakeExecutor(capacity=100, max_clusters=4)
+        srv = Server(ex, sym6=SYM6, policy=policy, fill=1e9)
+        srv.submit(running)
+        srv._admit(0.0)
+        srv.submit(big)
+        srv.submit(small)
+        srv._admit(0.0)
+        ids = [a.req.jid for a in srv.active]
+        assert (2 in ids) == small_first and 1 not in ids, (policy, ids)
+        res = srv.run([])
+        for r in (running, big, small):
+            p, v, _ = _solo_oracle(r)
+            assert np.array_equal(res[r.jid].pos, p), (policy, r.jid)
