@@ -82,14 +82,12 @@ def pair_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(prec, tile=None, workload="c3"):
-    """HBM bytes per pair-kernel launch from the committed counter summary of this workload
-    (FETCH_SIZE and WRITE_SIZE calibrated against a plain copy), or None if the kernel source or
-    the launch shape has changed since the counters were taken or no summary exists."""
+def profile_summary(prec, tile=None, workload="c3"):
+    """Fields of the committed counter summary of this workload's pair kernel, or None if there is
+    none, or the kernel sources or the launch shape have changed since the counters were taken."""
     if workload not in PROFILE_TAG:
         return None
     path = os.path.join(ROOT, "profiles", "pair_%s_%s.md" % (prec, PROFILE_TAG[workload]))
-    src = PAIR_SOURCES
     if not os.path.exists(path):
         return None
     fields = {}
@@ -98,13 +96,19 @@ def traffic_from_profile(prec, tile=None, workload="c3"):
             k, v = line[2:].split(":", 1)
             v = v.split()
             fields[k.strip()] = v[0].strip("`") if v else ""
-    h = pair_source_hash()
-    if fields.get("kernel_source_sha256") != h:
+    if fields.get("kernel_source_sha256") != pair_source_hash():
         return None
     if tile is not None and fields.get("tile") != ",".join(str(v) for v in tile):
         return None
+    return fields
+
+
+def traffic_from_profile(prec, tile=None, workload="c3"):
+    """HBM bytes per pair-kernel launch (FETCH_SIZE and WRITE_SIZE calibrated against a plain
+    copy) from the committed summary, or None (see profile_summary)."""
+    f = profile_summary(prec, tile, workload)
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(f["hbm_bytes_per_launch"]) if f else None
     except (KeyError, ValueError):
         return None
 
@@ -198,14 +202,35 @@ def cpu_baseline(batch, pos_all, target_s, a_gpu):
         ref = ref + ae
         absa = absa + np.linalg.norm(ae, axis=1)
     err = np.linalg.norm(a_gpu[:rows] - ref, axis=1) / absa
+    cores = oracle.num_threads()
+    # one thread, on a sample of about 3 s
+    oracle.set_threads(1)
+    rows1 = max(1, min(n, int(3.0 * rows / (max(el, 1e-6) * max(cores, 1)))))
+    t0 = time.perf_counter()
+    oracle.accel(pos, mass, batch.G, eps, rows=(0, rows1))
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {
         "value": inter / el / 1e9,
         "unit": "G pair-interactions/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": "rows [0,%d) of the first cluster (N=%d) against all its sources, one FP64 force evaluation, "
                   "%.1f s" % (rows, n, el),
+        "single_thread_value": rows1 * n / el1 / 1e9,
+        "single_thread_sample": "rows [0,%d), %.1f s" % (rows1, el1),
+        "cpu_model": _cpu_model(),
     }, {"rows": rows, "max": float(err.max()), "median": float(np.median(err))}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def mode_errors(batch, accel_init, nrows):
@@ -220,10 +245,50 @@ def mode_errors(batch, accel_init, nrows):
         ae, _ = oracle.ext_field(batch.pos[:nrows], batch.G, batch.galaxy)
         ref = ref + ae
         absa = absa + np.linalg.norm(ae, axis=1)
-    out = {}
-    for m, a in accel_init.items():
-        err = np.linalg.norm(a - ref, axis=1) / absa
-        out[m] = {"rows": nrows, "max": float(err.max()), "median": float(np.median(err))}
+    return {m: _err_stats(a, ref, absa) for m, a in accel_init.items()}
+
+
+def _err_stats(a, ref, absa):
+    """err_i = |a_i - a_ref,i| / S_i (max, median) and max_i |a_i - a_ref,i| / a_rms of the rows."""
+    import numpy as np
+    d = np.linalg.norm(a - ref, axis=1)
+    arms = float(np.sqrt(np.mean(np.sum(ref * ref, axis=1))))
+    err = d / absa
+    return {"rows": int(a.shape[0]), "max": float(err.max()), "median": float(np.median(err)),
+            "max_over_arms": float(d.max() / arms)}
+
+
+def sampled_state_errors(batch, modes, integrator, dt, steps, nrows, torch):
+    """Accuracy of every mode's force evaluation on states of the FP64-mode trajectory (steps 0,
+    steps/2 and steps), each against the oracle on the same state (first nrows particles of the
+    first cluster)."""
+    import numpy as np
+    import oracle
+    from paper_1003_3896_amd import nbody
+    n = int(batch.offsets[1])
+    ref_sim = nbody.Simulation(batch, "fp64")
+    ref_sim.accel()
+    sims = {m: nbody.Simulation(batch, m) for m in modes}
+    out, done = {}, 0
+    for target in sorted({0, steps // 2, steps}):
+        if target > done:
+            ref_sim.step(integrator, dt, target - done)
+            done = target
+        torch.cuda.synchronize()
+        pos = ref_sim.pos.cpu().numpy()
+        ref, absa = oracle.accel(pos[:n], batch.mass[:n], batch.G, float(batch.eps[0]), rows=(0, nrows),
+                                 want_abs=True)
+        if batch.field[0]:
+            ae, _ = oracle.ext_field(pos[:nrows], batch.G, batch.galaxy)
+            ref = ref + ae
+            absa = absa + np.linalg.norm(ae, axis=1)
+        row = {}
+        for m, s in sims.items():
+            s.pos.copy_(ref_sim.pos)
+            row[m] = _err_stats(s.accel().cpu().numpy()[:nrows], ref, absa)
+        out[str(target)] = row
+    for s in list(sims.values()) + [ref_sim]:
+        s.close()
     return out
 
 
@@ -353,6 +418,8 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / fam_peak, 4),
         "traffic": traffic_from_profile(prec, tile_used, args.workload),
+        "busy_clock_ghz_profiled": (lambda f: float(f["busy_clock_ghz"]) if f and "busy_clock_ghz" in f else None)(
+            profile_summary(prec, tile_used, args.workload)),
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
                  "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
         "kernel": "pair (%s)" % prec,
@@ -436,6 +503,9 @@ def main():
         result["cpu_baseline"] = cb
         result["parity_sample"] = parity
         result["accel_error_initial_state"] = mode_errors(batch, accel_init, nrows)
+        if args.workload in ("c2", "c3"):
+            result["accel_error_on_fp64_trajectory"] = sampled_state_errors(
+                batch, list(accel_init), integrator, dt, args.steps, nrows, torch)
     print(json.dumps(result), flush=True)
 
 

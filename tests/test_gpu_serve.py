@@ -20,12 +20,15 @@ def _reqs(prec_tag, count=10):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32ds", "fp64"])
-def test_alone_equals_in_mix(prec):
+@pytest.mark.parametrize("prec,policy,fill", [("fp32ds", "srpt", 2.0 ** 30), ("fp32ds", "srpt", 4e6),
+                                              ("fp32ds", "all", 0.0), ("fp64", "srpt", 2.0 ** 30)])
+def test_alone_equals_in_mix(prec, policy, fill):
+    """20 jobs (sizes 128..3000 across two size classes, both integrators, field on some) served
+    together, with queueing, reordering and partial rounds, give bitwise their results alone."""
     torch_dev()
-    reqs = _reqs(prec)
+    reqs = _reqs(prec, count=20)
     ex = HipExecutor(capacity=12000, max_clusters=6, prec=prec, energy_prec="fp64")
-    mix = Server(ex).run(reqs)  # capacity forces queueing: jobs join while others run
+    mix = Server(ex, policy=policy, fill=fill).run(reqs)  # capacity forces queueing
     for r in reqs:
         assert mix[r.jid].status == "done"
         alone = Server(ex).run([r])[r.jid]
