@@ -33,6 +33,13 @@
  *              and the coordinate difference of each pair is formed from both parts, the
  *              precision-recovery scheme of Sect. 5.2.
  *   NB_FP64    all FP64.
+ *   NB_FP32DL  the accuracy of NB_FP32DS at close to the cost of NB_FP32C: each evaluation sorts
+ *              every cluster's particles along a Morton curve of their FP64 positions; each pair
+ *              work item takes coordinates relative to the centre of its own i-particles' bounding
+ *              box; a j-tile all of whose sources lie at least one box diagonal from that centre
+ *              is computed in FP32 on those local coordinates (coordinate-difference error at
+ *              most 2^-22 relative), any other in double-single as NB_FP32DS.  Sums folded into
+ *              FP64 per tile as in NB_FP32C.
  *
  * Errors
  *   Every function returns NB_OK (0) or a negative status.  All argument checks run on the host
@@ -65,7 +72,7 @@ enum {
   NB_ERR_NONFINITE = -5    /* reserved: a diagnostic found a non-finite value */
 };
 
-enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3 };
+enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3, NB_FP32DL = 4 };
 
 /* External galaxy (Eq. 3, F_ext), G-scaled except for the halo:
  *   Hernquist bulge      Phi_b = -G Mb / (r + ab)
@@ -84,7 +91,7 @@ typedef struct {
   const double* eps;      /* [B] softening lengths, each >= 0 and finite */
   const uint8_t* field;   /* [B] nonzero = add the galaxy field to that cluster; NULL = none */
   nbody_galaxy galaxy;    /* used by clusters whose field flag is set */
-  int32_t prec;           /* NB_FP32 .. NB_FP64 */
+  int32_t prec;           /* NB_FP32 .. NB_FP32DL */
 } nbody_system;
 
 /* Create a context bound to HIP device `device` (>= 0).  The context caches launch plans and
@@ -98,10 +105,11 @@ void nbody_destroy(nbody_ctx* ctx);
 /* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
  * nbody_last_error() says why): 8 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
- * about 2^19/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
- * 512..131071 particles are split), plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned; its contents
- * are the library's between calls (the caller must not modify it while calls using it are in
- * flight). */
+ * about 2^21/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
+ * 512..2^20 particles are split), plus 48 bytes per particle and 4 KiB per 2048 particles for
+ * the sort of NB_FP32DL, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
+ * its contents are the library's between calls (the caller must not modify it while calls using
+ * it are in flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);
 
 /* An upper bound of nbody_workspace_bytes over every system of at most max_particles particles
@@ -171,7 +179,7 @@ const char* nbody_last_error(void);
 /* ---- Tuning and instrumentation (not part of the method) ---------------------------------- */
 
 /* Pair-kernel launch shape for one precision family and cluster-size class:
- *   prec  NB_FP32 / NB_FP32C (share a kernel), NB_FP32DS or NB_FP64
+ *   prec  NB_FP32 / NB_FP32C (share a kernel), NB_FP32DS, NB_FP64 or NB_FP32DL
  *   nclass 0: largest cluster < 2048 particles, 1: < 32768, 2: larger
  *   k     i-particles per lane; waves_per_group  wavefronts sharing the same i-particles, each
  *         taking 1/waves_per_group of every j-tile; (k, waves_per_group) in {(1,1), (1,2), (1,4),

@@ -23,10 +23,12 @@ SHAPES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4)]
 PHASED = {(1, 4, 256), (2, 2, 256), (2, 4, 128), (2, 4, 256)}
 TILES = [128, 256]
 BLOCKS_PER_CU = [2, 4, 8]
-FAMILY = {"fp32": "f32", "fp32c": "f32", "fp32ds": "ds", "fp64": "f64"}
+FAMILY = {"fp32": "f32", "fp32c": "f32", "fp32ds": "ds", "fp64": "f64", "fp32dl": "dl"}
+# shapes the local double-single family does not compile
+NOT_DL = {(1, 1), (1, 2)}
 # error bound a shape must meet: max_i |a_i - a_fp64,i| / (|a_fp64,i| + a_rms), against the library's
 # own FP64 evaluation of the same state (the tests pin that one to the oracle)
-BOUND = {"fp32": float("inf"), "fp32c": float("inf"), "fp32ds": 1e-6, "fp64": 1e-12}
+BOUND = {"fp32": float("inf"), "fp32c": float("inf"), "fp32ds": 1e-6, "fp64": 1e-12, "fp32dl": 1e-6}
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
 
 
@@ -60,10 +62,12 @@ def sweep(batch, prec: str, shapes=None, tiles=None, bpcs=None, reps: int = 3, s
     out = []
     cands = []
     for (k, w) in shapes:
+        if prec == "fp32dl" and (k, w) in NOT_DL:
+            continue
         for t in tiles:
             for bpc in bpcs:
                 cands.append((k, w, t, bpc, 0))
-                if prec != "fp64" and (k, w, t) in PHASED:
+                if prec not in ("fp64", "fp32dl") and (k, w, t) in PHASED:
                     cands.append((k, w, t, bpc, 1))
     for (k, w, t, bpc, ph) in cands:
         nbody.nbody_set_tile(sim.ctx, prec, nclass, k, w, t, bpc, ph)
@@ -115,14 +119,16 @@ def apply(ctx, arch: str = "gfx950", path: str = CACHE, fixed_tile: Optional[Dic
         a, fam, ncl = key.split("/")
         if a != arch:
             continue
-        prec = {"f32": "fp32c", "ds": "fp32ds", "f64": "fp64"}[fam]
+        prec = {"f32": "fp32c", "ds": "fp32ds", "f64": "fp64", "dl": "fp32dl"}[fam]
         tile, w = cfg["tile"], cfg["w"]
         k = cfg["k"]
         if fixed_tile and fam in fixed_tile:
             tile, w = fixed_tile[fam]
-            if (k, w) not in SHAPES:
+            if fam == "dl":
+                k = 2  # the local family's item tile (K, W) also shapes its arithmetic
+            elif (k, w) not in SHAPES:
                 k = 1
-        ph = cfg.get("phase", 0) if (k, w, tile) in PHASED and fam != "f64" else 0
+        ph = cfg.get("phase", 0) if (k, w, tile) in PHASED and fam in ("f32", "ds") else 0
         nbody.nbody_set_tile(ctx, prec, int(ncl), k, w, tile, cfg["bpc"], ph)
         n += 1
     return n
@@ -138,7 +144,7 @@ def representative(nclass: int):
     return inputs.c3()
 
 
-def tune_all(precs=("fp32c", "fp32ds", "fp64"), classes=(0, 1, 2), path: str = CACHE, verbose: bool = True) -> Dict:
+def tune_all(precs=("fp32c", "fp32ds", "fp64", "fp32dl"), classes=(0, 1, 2), path: str = CACHE, verbose: bool = True) -> Dict:
     """Sweep every (precision family, size class) on its representative workload and cache the
     fastest shape that passes the accuracy gate."""
     out = {}

@@ -28,6 +28,34 @@ __device__ __forceinline__ void block_reduce(double (&val)[V], double (*sh)[kBlo
   for (int q = 0; q < V; ++q) val[q] = sh[q][0];
 }
 
+// Fixed-order tree reduction of V minima and V maxima per thread; result valid in thread 0.
+template <int V>
+__device__ __forceinline__ void block_minmax(double (&mn)[V], double (&mx)[V], double (*sh)[kBlock]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    sh[q][t] = mn[q];
+    sh[V + q][t] = mx[q];
+  }
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        sh[q][t] = fmin(sh[q][t], sh[q][t + s]);
+        sh[V + q][t] = fmax(sh[V + q][t], sh[V + q][t + s]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    mn[q] = sh[q][0];
+    mx[q] = sh[V + q][0];
+  }
+}
+
 // Returns true in every thread of the block that finished cluster `cl` last (after its partial
 // was published by thread 0).
 __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks) {
@@ -41,11 +69,12 @@ __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks)
 }
 
 // Kick (v += kick_pre a) and drift (x += drift v) of one chunk (when `update`), then per cluster
-// the reference point ref = sum m x / sum m of the (new) positions and whether all masses are
-// equal (mconst = that mass, else 0), combined in the last block of the cluster.  Always launched
-// before the pair kernel, whose work counter it clears.
+// the reference point ref = sum m x / sum m of the (new) positions, whether all masses are equal
+// (mconst = that mass, else 0) and the bounding box, combined in the last block of the cluster.
+// Always launched before the pair kernel, whose work counter it clears.
+constexpr int kPartials = 11;
 __global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
-  __shared__ double sh[5][kBlock];
+  __shared__ double sh[6][kBlock];
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.item_counter = 0;  // the pair kernel that follows starts at item 0
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
@@ -87,22 +116,46 @@ __global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
     }
   }
   double val[5] = {m * x[0], m * x[1], m * x[2], m, odd};
+  double mn[3], mx[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = valid ? x[d] : INFINITY;
+    mx[d] = valid ? x[d] : -INFINITY;
+  }
   block_reduce<5>(val, sh);
-  if (t == 0)
-    for (int q = 0; q < 5; ++q) a.partials[(size_t)blockIdx.x * 5 + q] = val[q];
+  block_minmax<3>(mn, mx, sh);
+  if (t == 0) {
+    double* p = a.partials + (size_t)blockIdx.x * kPartials;
+    for (int q = 0; q < 5; ++q) p[q] = val[q];
+    for (int d = 0; d < 3; ++d) {
+      p[5 + d] = mn[d];
+      p[8 + d] = mx[d];
+    }
+  }
   if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
   double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int q = t; q < c.nchunks; q += kBlock) {
-    const double* p = a.partials + (size_t)(c.chunk0 + q) * 5;
+    const double* p = a.partials + (size_t)(c.chunk0 + q) * kPartials;
     for (int r = 0; r < 5; ++r) tot[r] += p[r];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], p[5 + d]);
+      hi[d] = fmax(hi[d], p[8 + d]);
+    }
   }
   __syncthreads();
   block_reduce<5>(tot, sh);
+  block_minmax<3>(lo, hi, sh);
   if (t == 0) {
     const double M = tot[3];
     a.ref[ch.cluster] = M > 0.0 ? make_double4(tot[0] / M, tot[1] / M, tot[2] / M, M)
                                 : make_double4(0.0, 0.0, 0.0, 0.0);
     a.mconst[ch.cluster] = tot[4] == 0.0 ? a.mass[c.off] : 0.0;
+    double* b = a.box + 6 * (size_t)ch.cluster;
+    for (int d = 0; d < 3; ++d) {
+      b[d] = lo[d];
+      b[3 + d] = hi[d];
+    }
     a.chunk_counter[ch.cluster] = 0;
   }
 }
@@ -179,8 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(Args a, int potmode, int kic
   const DevCluster c = a.cl[ch.cluster];
   const int t = threadIdx.x;
   if (c.split <= 1 || t >= ch.count) return;
-  const int li = ch.start + t;
-  const long long gi = c.off + li;
+  const int li = ch.start + t;  // position in the cluster's (sorted) order
+  const long long gi = particle_index(a, c, li);
   const bool r32 = a.prec == NB_FP32;
   double ax = 0.0, ay = 0.0, az = 0.0, pt = 0.0;
   float fx = 0.0f, fy = 0.0f, fz = 0.0f, fp = 0.0f;

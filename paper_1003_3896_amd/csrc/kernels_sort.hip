@@ -1,0 +1,187 @@
+// Morton-order sort of every cluster's particles for the NB_FP32DL mode (gfx950).
+//
+// The pair kernel of that mode centres each work item's coordinates on its own i-particles, which
+// pays off only when the particles of an i-tile (and of a j-tile) lie close together; sorting
+// along a Morton curve of the positions makes consecutive particles spatial neighbours.  The sort
+// is a stable least-significant-digit radix sort of 30-bit keys (10 bits per axis, relative to the
+// cluster's bounding box) in three passes of 10 bits.  Sort tiles never span clusters, so every
+// cluster is sorted on its own, and the result depends only on that cluster's positions: ties
+// keep the particles' own order, and no step depends on the timing of other blocks.
+#include "nb_internal.h"
+
+namespace nb {
+
+namespace {
+
+// Spreads the low 10 bits of v so that bit b moves to bit 3b.
+__device__ __forceinline__ unsigned spread3(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ unsigned cell(double x, double lo, double scale) {
+  const double q = (x - lo) * scale;
+  return q <= 0.0 ? 0u : q >= (double)(kRadix - 1) ? (unsigned)(kRadix - 1) : (unsigned)q;
+}
+
+// Keys of one O(N) chunk: Morton code of the position in the cluster's box, value = local index.
+__global__ __launch_bounds__(kBlock) void k_keys(Args a) {
+  const Chunk ch = a.chunks[blockIdx.x];
+  const DevCluster c = a.cl[ch.cluster];
+  const int t = threadIdx.x;
+  if (t >= ch.count) return;
+  const int l = ch.start + t;
+  const long long g = c.off + l;
+  const double* b = a.box + 6 * (size_t)ch.cluster;
+  unsigned code = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double ext = b[3 + d] - b[d];
+    const double scale = ext > 0.0 ? (double)kRadix / ext : 0.0;
+    code |= spread3(cell(a.pos[3 * g + d], b[d], scale)) << d;
+  }
+  a.skey[0][g] = code;
+  a.sval[0][g] = l;
+}
+
+// Digit counts of one sort tile.
+__global__ __launch_bounds__(kBlock) void k_rhist(Args a, int src, int shift) {
+  __shared__ int h[kRadix];
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) h[d] = 0;
+  __syncthreads();
+  const Chunk st = a.stiles[blockIdx.x];
+  const long long base = a.cl[st.cluster].off + st.start;
+  for (int e = threadIdx.x; e < st.count; e += kBlock) atomicAdd(&h[(a.skey[src][base + e] >> shift) & (kRadix - 1)], 1);
+  __syncthreads();
+  int* out = a.shist + (size_t)blockIdx.x * kRadix;
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) out[d] = h[d];
+}
+
+// Per cluster (one block): turns the digit counts of its sort tiles into each tile's first
+// destination per digit: all smaller digits of the cluster, then the same digit in earlier tiles.
+constexpr int kDigitsPerThread = kRadix / kBlock;
+__global__ __launch_bounds__(kBlock) void k_rscan(Args a) {
+  const DevCluster c = a.cl[blockIdx.x];
+  const int t = threadIdx.x;
+  int run[kDigitsPerThread];
+#pragma unroll
+  for (int r = 0; r < kDigitsPerThread; ++r) run[r] = 0;
+  // exclusive prefix over the tiles, digit by digit (loads batched to overlap their latency)
+  constexpr int kBatch = 8;
+  for (int q0 = 0; q0 < c.nstiles; q0 += kBatch) {
+    int v[kBatch][kDigitsPerThread];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int r = 0; r < kDigitsPerThread; ++r)
+        v[b][r] = q0 + b < c.nstiles ? a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] : 0;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int r = 0; r < kDigitsPerThread; ++r) {
+        if (q0 + b < c.nstiles) a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] = run[r];
+        run[r] += v[b][r];
+      }
+  }
+  // exclusive prefix over the digits: within the thread, then across threads (fixed-order scan)
+  __shared__ int sum[kBlock];
+  int pre[kDigitsPerThread], tot = 0;
+#pragma unroll
+  for (int r = 0; r < kDigitsPerThread; ++r) {
+    pre[r] = tot;
+    tot += run[r];
+  }
+  sum[t] = tot;
+  __syncthreads();
+  for (int s = 1; s < kBlock; s <<= 1) {
+    const int x = t >= s ? sum[t - s] : 0;
+    __syncthreads();
+    sum[t] += x;
+    __syncthreads();
+  }
+  const int base_t = sum[t] - tot;
+  for (int q0 = 0; q0 < c.nstiles; q0 += kBatch) {
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int r = 0; r < kDigitsPerThread; ++r)
+        if (q0 + b < c.nstiles) a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] += base_t + pre[r];
+  }
+}
+
+// Stable scatter of one sort tile: elements are ranked in tile order, 256 per round; inside a
+// wave the lanes holding the same digit are found with one ballot per digit bit, and the four
+// waves take their turns on the running per-digit destinations.
+__global__ __launch_bounds__(kBlock) void k_rscatter(Args a, int src, int shift) {
+  __shared__ int dst[kRadix];
+  const Chunk st = a.stiles[blockIdx.x];
+  const long long base = a.cl[st.cluster].off;
+  const int* offs = a.shist + (size_t)blockIdx.x * kRadix;
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) dst[d] = offs[d];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int r0 = 0; r0 < st.count; r0 += kBlock) {
+    const int e = r0 + threadIdx.x;
+    const bool valid = e < st.count;
+    unsigned key = 0;
+    int val = 0;
+    if (valid) {
+      key = a.skey[src][base + st.start + e];
+      val = a.sval[src][base + st.start + e];
+    }
+    const int digit = (int)((key >> shift) & (kRadix - 1));
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (digit >> b) & 1;
+      const unsigned long long m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    const bool leader = valid && (peers & below) == 0;
+    __syncthreads();  // dst[] holds the destinations after the previous round (and waves)
+    for (int w = 0; w < kBlock / 64; ++w) {
+      if (wave == w && valid) {
+        const int pos = dst[digit] + rank;
+        a.skey[src ^ 1][base + pos] = key;
+        a.sval[src ^ 1][base + pos] = val;
+      }
+      __syncthreads();
+      if (wave == w && leader) dst[digit] += __popcll(peers);
+      __syncthreads();
+    }
+  }
+}
+
+// The FP64 state of the sorted order, so the pair kernel streams its j-tiles contiguously.
+__global__ __launch_bounds__(kBlock) void k_gather(Args a) {
+  const Chunk ch = a.chunks[blockIdx.x];
+  const DevCluster c = a.cl[ch.cluster];
+  const int t = threadIdx.x;
+  if (t >= ch.count) return;
+  const long long l = c.off + ch.start + t;
+  const long long g = c.off + a.sval[1][l];
+  a.spos[l] = make_double4(a.pos[3 * g], a.pos[3 * g + 1], a.pos[3 * g + 2], a.mass[g]);
+}
+
+}  // namespace
+
+hipError_t launch_sort(const Args& a, int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys, dim3(a.nchunks), dim3(kBlock), 0, s, a);
+  int src = 0;
+  for (int shift = 0; shift < 3 * kRadixBits; shift += kRadixBits) {
+    hipLaunchKernelGGL(k_rhist, dim3(a.nstiles), dim3(kBlock), 0, s, a, src, shift);
+    hipLaunchKernelGGL(k_rscan, dim3(B), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rscatter, dim3(a.nstiles), dim3(kBlock), 0, s, a, src, shift);
+    src ^= 1;
+  }
+  // three passes: the sorted order is in buffer 1
+  hipLaunchKernelGGL(k_gather, dim3(a.nchunks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace nb

@@ -9,8 +9,15 @@ namespace nb {
 constexpr int kBlock = 256;
 constexpr int kChunk = 256;
 
-// Precision families of the pair kernel.
-enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2 };
+// Precision families of the pair kernel (FAM_DL: double-single near j-tiles, FP32 on coordinates
+// centred on the i-tile for far ones, particles in Morton order).
+enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2, FAM_DL = 3 };
+constexpr int kFamilies = 4;
+
+// Morton sort of the NB_FP32DL mode: particles per sort tile (one block), radix digit bits.
+constexpr int kSortTile = 2048;
+constexpr int kRadixBits = 10;
+constexpr int kRadix = 1 << kRadixBits;
 
 // Per-cluster descriptor in device memory (uploaded with every call).
 struct DevCluster {
@@ -24,12 +31,14 @@ struct DevCluster {
   int nchunks;         // O(N) chunks of the cluster
   int split;           // the j-sum of every particle is split into this many ranges (1 = none)
   int jlen;            // sources per range (the last range may be shorter)
-  int pad;
+  int stile0;          // first sort tile of the cluster (NB_FP32DL)
+  int nstiles;         // sort tiles of the cluster
 };
 constexpr int kFlagField = 1;     // add the galaxy field
 constexpr int kFlagMaskSelf = 2;  // eps == 0: the j = i term must be excluded explicitly
 
-// O(N) chunk: kChunk consecutive particles of one cluster.
+// O(N) chunk: kChunk consecutive particles of one cluster (also used for sort tiles of
+// kSortTile particles).
 struct Chunk {
   int cluster, start, count, pad;
 };
@@ -52,7 +61,18 @@ struct Args {
   int nitems;
   int* item_counter;   // dynamic work distribution of the persistent pair kernel
   int* chunk_counter;  // [B] chunks finished per cluster (last-block reductions)
-  double* partials;    // [nchunks][5] chunk sums: m x, m y, m z, m, count of masses != the cluster's first
+  double* partials;    // [nchunks][11] chunk sums m x, m y, m z, m, count of masses != the cluster's
+                       // first; then min x, y, z and max x, y, z
+  double* box;         // [B][6] bounding box of each cluster (min xyz, max xyz)
+  // Morton sort (NB_FP32DL): keys and local indices (double-buffered), per-tile digit counts and
+  // offsets, and the result: perm[off + l] = local index of the particle at sorted position l
+  const Chunk* stiles;
+  int nstiles;
+  unsigned* skey[2];
+  int* sval[2];
+  int* shist;          // [nstiles][kRadix]
+  const int* perm;     // null: particles in their own order
+  double4* spos;       // [Ntot] (x, y, z, m) in sorted order (NB_FP32DL), else null
   double* mconst;      // [B] the common mass of a cluster whose masses are all equal, else 0
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
   double4* part;       // partial sums (ax, ay, az, pot) of split clusters
@@ -86,6 +106,8 @@ hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, boo
                        hipStream_t s);
 hipError_t launch_energy(const Args& a, hipStream_t s);
 hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s);
+// Morton sort: leaves the permutation in sval[1] and the sorted (x, y, z, m) in spos
+hipError_t launch_sort(const Args& a, int B, hipStream_t s);
 
 
 bool tile_supported(int family, const TileCfg& t);
@@ -96,5 +118,11 @@ typedef void (*PairFn)(Args, int);
 PairFn pair_kernel_f32(const TileCfg& t, bool fold, bool mask, bool pot);
 PairFn pair_kernel_ds(const TileCfg& t, bool fold, bool mask, bool pot);
 PairFn pair_kernel_f64(const TileCfg& t, bool fold, bool mask, bool pot);
+PairFn pair_kernel_dl(const TileCfg& t, bool fold, bool mask, bool pot);
+
+// Index in the state arrays of the particle at (sorted) local position l of cluster c.
+__device__ __forceinline__ long long particle_index(const Args& a, const DevCluster& c, int l) {
+  return c.off + (a.perm ? a.perm[c.off + l] : l);
+}
 
 }  // namespace nb

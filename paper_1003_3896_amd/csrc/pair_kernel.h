@@ -17,9 +17,16 @@
 // it into FP64 after every tile; pure-FP32 mode keeps one FP32 sum.  The double-single family forms
 // each coordinate difference as (xj_hi - xi_hi) + (xj_lo - xi_lo): the hi difference is exact for
 // close pairs, so the difference carries FP32 relative accuracy however close the pair is.
+// The local family (particles in Morton order) centres every coordinate on the bounding box of
+// the work item's i-particles; a full j-tile that lies entirely at least one box diagonal D from
+// that centre is computed in plain FP32 on the local coordinates: rounding both
+// coordinates to FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction
+// by 2^-24 |d| more, at most 2^-22 |d| in all (R = D/2 <= |d|), so such a term is as accurate as
+// a double-single one up to a small factor; other shares run the double-single loop.
 //
-// The results for a particle depend only on its own cluster's data and on (T, W): never on the
-// other clusters of the batch, on K, on the number of blocks, or on which block took which item.
+// The results for a particle depend only on its own cluster's data and on (T, W) (in the local
+// family also on K, which sets the i-tile each coordinate frame is centred on): never on the other
+// clusters of the batch, on the number of blocks, or on which block took which item.
 #pragma once
 #include "nb_device.h"
 
@@ -38,6 +45,8 @@ struct PairLds<FAM_DS, T> {
   float4 lo[T];
   __device__ const float4& lo_at(int i) const { return lo[i]; }
 };
+template <int T>
+struct PairLds<FAM_DL, T> : PairLds<FAM_DS, T> {};
 template <int T>
 struct PairLds<FAM_F64, T> {
   double4 r[T];
@@ -60,12 +69,18 @@ struct TileRaw {
 };
 
 template <int T>
-__device__ __forceinline__ TileRaw fetch_tile(const Args& a, long long base, int cnt) {
+__device__ __forceinline__ TileRaw fetch_tile(const Args& a, const DevCluster& c, int j, int cnt) {
   const int tid = threadIdx.x;
   TileRaw r;
   r.valid = tid < T && tid < cnt;
-  if (r.valid) {
-    const long long g = base + tid;
+  if (r.valid && a.spos) {  // sorted copy: contiguous 32-byte records
+    const double4 q = a.spos[c.off + j + tid];
+    r.x = q.x;
+    r.y = q.y;
+    r.z = q.z;
+    r.m = q.w;
+  } else if (r.valid) {
+    const long long g = c.off + j + tid;
     r.x = a.pos[3 * g];
     r.y = a.pos[3 * g + 1];
     r.z = a.pos[3 * g + 2];
@@ -91,14 +106,14 @@ __device__ __forceinline__ void store_tile(const Args& a, PairLds<FAM, T>& sh, c
   } else {
     if (!r.valid) {
       sh.hi[tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-      if constexpr (FAM == FAM_DS) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if constexpr (FAM != FAM_F32) sh.lo[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     } else if (a.prec == 0) {
       sh.hi[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)w);
     } else {
       const double dx = r.x - ref.x, dy = r.y - ref.y, dz = r.z - ref.z;
       const float hx = (float)dx, hy = (float)dy, hz = (float)dz;
       sh.hi[tid] = make_float4(hx, hy, hz, (float)w);
-      if constexpr (FAM == FAM_DS)
+      if constexpr (FAM != FAM_F32)
         sh.lo[tid] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
     }
   }
@@ -159,7 +174,7 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
   for (int k = 0; k < K; ++k) {
     const int li = ibase + k * 64;
     if (li >= c.n) continue;
-    const long long gi = c.off + li;
+    const long long gi = particle_index(a, c, li);
     finish_particle(a, c, item.cluster, gi, ax[k], ay[k], az[k], round32, kick);
     if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt[k]) : -a.G * pt[k];
   }
@@ -200,13 +215,12 @@ __device__ __forceinline__ void interact32(const float4 pj, const float4 pl, con
 }
 
 // The pair terms of this wave's share [u0, u0 + TW) of one full LDS tile (T records).
-template <int FAM, int K, int TW, int T, bool MASK, bool POT, bool PH, bool EQ>
-__device__ __forceinline__ void full_tile_terms(const PairLds<FAM, T>& sh, int u0, int j0, const float (&xi)[K],
+template <class LDS, bool DS, int K, int TW, int T, bool MASK, bool POT, bool PH, bool EQ>
+__device__ __forceinline__ void full_tile_terms(const LDS& sh, int u0, int j0, const float (&xi)[K],
                                            const float (&yi)[K], const float (&zi)[K], const float (&xl)[K],
                                            const float (&yl)[K], const float (&zl)[K], float e2, float (&ax)[K],
                                            float (&ay)[K], float (&az)[K], float (&bx)[K], float (&by)[K],
                                            float (&bz)[K], float (&pt)[K], const int (&li)[K]) {
-  constexpr bool DS = FAM == FAM_DS;
   if (PH) {  // rsq-grouped phases
     constexpr int BJ = 8 / K;
     for (int u = u0; u < u0 + TW; u += BJ) {
@@ -272,17 +286,19 @@ __device__ __forceinline__ void full_tile_terms(const PairLds<FAM, T>& sh, int u
 template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT, bool PH = false>
 __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
   static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
-  constexpr bool DS = FAM == FAM_DS;
+  constexpr bool LOC = FAM == FAM_DL;         // local centring + near/far tiles
+  constexpr bool DS = FAM == FAM_DS || LOC;  // double-single records and i-particles
   constexpr int TW = T / W;      // records per wave per tile
   __shared__ PairLds<FAM, T> sh;
   __shared__ double red[W > 1 ? 4 * 64 * K * 4 : 1];
   __shared__ int s_item;
+  __shared__ double s_box[LOC ? 4 * 6 : 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / W, sub = wave % W;
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
     const PairItem item = a.items[it];
     const DevCluster c = a.cl[item.cluster];
-    const double4 ref = a.ref[item.cluster];
+    double4 ref = a.ref[item.cluster];
     const double mc = a.mconst[item.cluster];  // != 0: every mass of the cluster equals mc
     const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
@@ -290,10 +306,50 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K];
     double Ax[K], Ay[K], Az[K], Pt[K];
     int li[K];
+    long long gidx[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       li[k] = ibase + k * 64;
-      const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
+      gidx[k] = particle_index(a, c, li[k] < c.n ? li[k] : c.n - 1);
+    }
+    double far2 = INFINITY;  // LOC: a j-record at |x_j - ref|^2 >= far2 is far from every i-particle
+    if constexpr (LOC) {
+      // bounding box of the item's i-particles (FP64); ref = its centre, far2 = its diagonal^2
+      double v[6];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        v[d] = v[3 + d] = a.pos[3 * gidx[0] + d];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          v[d] = fmin(v[d], a.pos[3 * gidx[k] + d]);
+          v[3 + d] = fmax(v[3 + d], a.pos[3 * gidx[k] + d]);
+        }
+      }
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          v[d] = fmin(v[d], __shfl_xor(v[d], m));
+          v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], m));
+        }
+      __syncthreads();  // s_box of the previous item has been read
+      if (lane == 0)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) s_box[wave * 6 + d] = v[d];
+      __syncthreads();
+      double lo[3], hi[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(fmin(s_box[d], s_box[6 + d]), fmin(s_box[12 + d], s_box[18 + d]));
+        hi[d] = fmax(fmax(s_box[3 + d], s_box[9 + d]), fmax(s_box[15 + d], s_box[21 + d]));
+      }
+      ref = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]), 0.0);
+      const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+      far2 = (dx * dx + dy * dy + dz * dz) * (1.0 + 1e-6);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const long long gi = gidx[k];
       float4 p, q;
       record32(a, gi, ref, p, q);
       xi[k] = p.x;
@@ -310,20 +366,39 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
     }
     const float e2 = c.eps2f;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
-    TileRaw raw = fetch_tile<T>(a, c.off + jb, min(T, je - jb));
+    TileRaw raw = fetch_tile<T>(a, c, jb, min(T, je - jb));
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
       store_tile<FAM, T>(a, sh, raw, ref, eq);
-      __syncthreads();
-      if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
+      bool far = false;
+      if constexpr (LOC) {
+        // a full tile is far when every record of it is (then the FP32 difference of the local
+        // coordinates is within 2^-22 relative of the exact one); decided for the whole block, so
+        // its waves take the same path and meet at the tile barriers together
+        bool ok = cnt == T;
+        if (ok && threadIdx.x < T) {
+          const double dx = raw.x - ref.x, dy = raw.y - ref.y, dz = raw.z - ref.z;
+          ok = dx * dx + dy * dy + dz * dz >= far2;
+        }
+        far = __syncthreads_and(ok);
+      } else {
+        __syncthreads();
+      }
+      if (j0 + T < je) raw = fetch_tile<T>(a, c, j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
-      if (cnt == T && eq)
-        full_tile_terms<FAM, K, TW, T, MASK, POT, PH, true>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx,
-                                                            by, bz, pt, li);
+      if (LOC && far && eq)
+        full_tile_terms<PairLds<FAM, T>, false, K, TW, T, MASK, POT, false, true>(
+            sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx, by, bz, pt, li);
+      else if (LOC && far)
+        full_tile_terms<PairLds<FAM, T>, false, K, TW, T, MASK, POT, false, false>(
+            sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx, by, bz, pt, li);
+      else if (cnt == T && eq)
+        full_tile_terms<PairLds<FAM, T>, DS, K, TW, T, MASK, POT, PH, true>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2,
+                                                                            ax, ay, az, bx, by, bz, pt, li);
       else if (cnt == T)
-        full_tile_terms<FAM, K, TW, T, MASK, POT, PH, false>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx,
-                                                             by, bz, pt, li);
+        full_tile_terms<PairLds<FAM, T>, DS, K, TW, T, MASK, POT, PH, false>(sh, u0, j0, xi, yi, zi, xl, yl, zl, e2,
+                                                                             ax, ay, az, bx, by, bz, pt, li);
       else {  // partial tile: the stored weight (mass, or 1 / 0 for equal masses) zeroes the padding
         const int mine = min(TW, ((cnt - u0 + 7) & ~7));  // this wave's records, padded to 8
         for (int u = u0; u < u0 + mine; u += 8) {
@@ -430,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       li[k] = ibase + k * 64;
-      const long long gi = c.off + (li[k] < c.n ? li[k] : c.n - 1);
+      const long long gi = particle_index(a, c, li[k] < c.n ? li[k] : c.n - 1);
       const double4 p = record64(a, gi);
       xi[k] = p.x;
       yi[k] = p.y;
@@ -439,13 +514,13 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     }
     const double e2 = c.eps2;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
-    TileRaw raw = fetch_tile<T>(a, c.off + jb, min(T, je - jb));
+    TileRaw raw = fetch_tile<T>(a, c, jb, min(T, je - jb));
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
       store_tile<FAM_F64, T>(a, sh, raw, make_double4(0.0, 0.0, 0.0, 0.0), eq);
       __syncthreads();
-      if (j0 + T < je) raw = fetch_tile<T>(a, c.off + j0 + T, min(T, je - j0 - T));
+      if (j0 + T < je) raw = fetch_tile<T>(a, c, j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
       if (cnt == T && eq)
         terms64<K, T, MASK, POT, true>(sh, u0, TW, j0, xi, yi, zi, e2, ax, ay, az, pt, li);
@@ -472,7 +547,7 @@ PairFn pair_flags(bool fold, bool mask, bool pot) {
   if constexpr (FAM == FAM_F64) {
     if (mask) return pot ? k_pair64<K, W, T, true, true> : k_pair64<K, W, T, true, false>;
     return pot ? k_pair64<K, W, T, false, true> : k_pair64<K, W, T, false, false>;
-  } else if constexpr (FAM == FAM_DS) {
+  } else if constexpr (FAM == FAM_DS || FAM == FAM_DL) {
     if (mask) return pot ? k_pair32<FAM, K, W, T, true, true, true> : k_pair32<FAM, K, W, T, true, true, false>;
     return pot ? k_pair32<FAM, K, W, T, true, false, true> : k_pair32<FAM, K, W, T, true, false, false>;
   } else {
@@ -485,12 +560,12 @@ PairFn pair_flags(bool fold, bool mask, bool pot) {
   }
 }
 
-// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)}, T in {128, 256}; the
-// rsq-phased full-tile loop for the FP32 families' main shapes, used for folded sums without the
-// self mask or the potential.
+// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)} ((1,4), (2,2), (2,4) for the
+// local family), T in {128, 256}; the rsq-phased full-tile loop for the FP32 and double-single
+// families' main shapes, used for folded sums without the self mask or the potential.
 template <int FAM>
 PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
-  if constexpr (FAM != FAM_F64) {
+  if constexpr (FAM == FAM_F32 || FAM == FAM_DS) {
     if (t.phase && fold && !mask && !pot) {
 #define NB_PHASED(KK, WW, TT) \
   if (t.k == KK && t.w == WW && t.tile == TT) return k_pair32<FAM, KK, WW, TT, true, false, false, true>;
@@ -503,10 +578,12 @@ PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
   }
 #define NB_SHAPE(KK, WW, TT) \
   if (t.k == KK && t.w == WW && t.tile == TT) return pair_flags<FAM, KK, WW, TT>(fold, mask, pot);
-  NB_SHAPE(1, 1, 128)
-  NB_SHAPE(1, 1, 256)
-  NB_SHAPE(1, 2, 128)
-  NB_SHAPE(1, 2, 256)
+  if constexpr (FAM != FAM_DL) {
+    NB_SHAPE(1, 1, 128)
+    NB_SHAPE(1, 1, 256)
+    NB_SHAPE(1, 2, 128)
+    NB_SHAPE(1, 2, 256)
+  }
   NB_SHAPE(1, 4, 128)
   NB_SHAPE(1, 4, 256)
   NB_SHAPE(2, 2, 128)

@@ -60,7 +60,8 @@ const Sym6 kSym6;
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, items, counters, coef, ref, mconst, partials, epart, pot, part, total;
+  size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, part, skey, sval, shist,
+      spos, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -68,11 +69,13 @@ struct Plan {
   int B = 0;
   long long ntot = 0;
   int nchunks = 0;
+  int nstiles = 0;  // sort tiles (NB_FP32DL only)
   int maxn = 0;
   bool anymask = false;
   bool anysplit = false;
   std::vector<DevCluster> cl;
   std::vector<Chunk> chunks;
+  std::vector<Chunk> stiles;
   Layout L{};
 };
 
@@ -84,27 +87,25 @@ struct Slot {
 };
 
 // j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
-// on their own (about 2^19 / N ranges, a power of two, at most 8), each range at least 256 sources;
-// clusters of 2^17 particles or more are not split.
+// on their own, and short enough items for the persistent grid to balance large ones (about
+// 2^21 / N ranges, a power of two, at most 8, each range at least 256 sources).
 // Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
 #ifndef NB_MIN_RANGE
 #define NB_MIN_RANGE 256  // fewest sources in one j-range of a split cluster (a tuning constant)
 #endif
 #ifndef NB_SPLIT_CAP
-#define NB_SPLIT_CAP (1LL << 19)  // bound on N x ranges (partial sums kept per cluster)
-#endif
-#ifndef NB_SPLIT_BELOW
-#define NB_SPLIT_BELOW (1 << 17)  // from this size on, a cluster's i-tiles alone fill the chip
+#define NB_SPLIT_CAP (1LL << 21)  // bound on N x ranges (partial sums kept per cluster)
 #endif
 int split_of(int n) {
   int s = 1;
-  if (n >= NB_SPLIT_BELOW) return 1;
   while (s < 8 && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
   return s;
 }
 
 int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : 2; }
-int family_of(int prec) { return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ? FAM_DS : FAM_F32; }
+int family_of(int prec) {
+  return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ? FAM_DS : prec == NB_FP32DL ? FAM_DL : FAM_F32;
+}
 
 }  // namespace
 
@@ -123,7 +124,7 @@ struct nbody_ctx {
   hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<StepGraph> gcache;  // small LRU cache of captured graphs (most recent last)
-  TileCfg tiles[3][3];
+  TileCfg tiles[kFamilies][3];
   Slot slots[4];
   int next_slot = 0;
   bool timing = false;
@@ -173,7 +174,7 @@ int check_system(const nbody_system* sys) {
     if (!(std::isfinite(e) && e >= 0.0)) return fail(NB_ERR_ARG, "eps[%d] must be finite and >= 0", b);
   }
   if (!(std::isfinite(sys->G) && sys->G > 0.0)) return fail(NB_ERR_ARG, "G must be finite and > 0");
-  if (sys->prec < NB_FP32 || sys->prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", sys->prec);
+  if (sys->prec < NB_FP32 || sys->prec > NB_FP32DL) return fail(NB_ERR_ARG, "unknown precision mode %d", sys->prec);
   bool anyfield = false;
   if (sys->field)
     for (int b = 0; b < sys->nclusters; ++b) anyfield |= sys->field[b] != 0;
@@ -189,13 +190,15 @@ int check_system(const nbody_system* sys) {
   return NB_OK;
 }
 
-Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart) {
+Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart, int nstiles) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
   o = align_up(o + sizeof(DevCluster) * B);
   L.chunks = o;
   o = align_up(o + sizeof(Chunk) * nchunks);
+  L.stiles = o;
+  o = align_up(o + sizeof(Chunk) * nstiles);
   L.items = o;
   o = align_up(o + sizeof(PairItem) * nitems_max);
   L.counters = o;  // [B] chunk counters, the item counter, the finished-blocks counter
@@ -207,14 +210,24 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + sizeof(double4) * B);
   L.mconst = o;
   o = align_up(o + sizeof(double) * B);
+  L.box = o;
+  o = align_up(o + sizeof(double) * 6 * B);
   L.partials = o;
-  o = align_up(o + sizeof(double) * 5 * nchunks);
+  o = align_up(o + sizeof(double) * 11 * nchunks);
   L.epart = o;
   o = align_up(o + sizeof(double) * 16 * nchunks);
   L.pot = o;
   o = align_up(o + sizeof(double) * ntot);
   L.part = o;
   o = align_up(o + sizeof(double4) * npart);
+  L.skey = o;  // [2][ntot] (sort tiles present only)
+  o = align_up(o + (nstiles ? sizeof(unsigned) * 2 * (size_t)ntot : 0));
+  L.sval = o;  // [2][ntot]
+  o = align_up(o + (nstiles ? sizeof(int) * 2 * (size_t)ntot : 0));
+  L.shist = o;  // [nstiles][kRadix]
+  o = align_up(o + sizeof(int) * (size_t)nstiles * kRadix);
+  L.spos = o;  // [ntot] sorted (x, y, z, m)
+  o = align_up(o + (nstiles ? sizeof(double4) * (size_t)ntot : 0));
   L.total = o;
   return L;
 }
@@ -226,6 +239,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.B = sys->nclusters;
   p.cl.resize(p.B);
   p.chunks.clear();
+  p.stiles.clear();
+  const bool sorted = sys->prec == NB_FP32DL;
   p.maxn = 0;
   p.anymask = false;
   p.anysplit = false;
@@ -253,12 +268,19 @@ int build_plan(const nbody_system* sys, Plan& p) {
       p.anysplit = true;
     }
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
-    c.pad = 0;
+    c.stile0 = (int)p.stiles.size();
+    c.nstiles = 0;
+    if (sorted)
+      for (int s = 0; s < c.n; s += kSortTile) {
+        p.stiles.push_back(Chunk{b, s, std::min(kSortTile, c.n - s), 0});
+        ++c.nstiles;
+      }
     p.maxn = std::max(p.maxn, c.n);
   }
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart);
+  p.nstiles = (int)p.stiles.size();
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart, p.nstiles);
   return NB_OK;
 }
 
@@ -328,6 +350,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   blob.assign(up, 0);
   memcpy(blob.data() + L.cl, p.cl.data(), sizeof(DevCluster) * p.B);
   memcpy(blob.data() + L.chunks, p.chunks.data(), sizeof(Chunk) * p.nchunks);
+  if (p.nstiles) memcpy(blob.data() + L.stiles, p.stiles.data(), sizeof(Chunk) * p.nstiles);
   memcpy(blob.data() + L.items, items.data(), sizeof(PairItem) * items.size());
   if (coef3) memcpy(blob.data() + L.coef, coef3, coef_bytes);
   int rc = NB_OK;
@@ -349,6 +372,16 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.item_counter = reinterpret_cast<int*>(w + L.counters) + p.B;
 
   a.partials = reinterpret_cast<double*>(w + L.partials);
+  a.box = reinterpret_cast<double*>(w + L.box);
+  a.stiles = reinterpret_cast<const Chunk*>(w + L.stiles);
+  a.nstiles = p.nstiles;
+  a.skey[0] = reinterpret_cast<unsigned*>(w + L.skey);
+  a.skey[1] = a.skey[0] + p.ntot;
+  a.sval[0] = reinterpret_cast<int*>(w + L.sval);
+  a.sval[1] = a.sval[0] + p.ntot;
+  a.shist = reinterpret_cast<int*>(w + L.shist);
+  a.perm = p.nstiles ? a.sval[1] : nullptr;
+  a.spos = p.nstiles ? reinterpret_cast<double4*>(w + L.spos) : nullptr;
   a.mconst = reinterpret_cast<double*>(w + L.mconst);
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
@@ -361,7 +394,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.prec = sys->prec;
   P.tile = t;
   P.grid = std::max(1, std::min(a.nitems, ctx->cus * t.bpc));
-  P.centred = sys->prec == NB_FP32C || sys->prec == NB_FP32DS;
+  P.centred = sys->prec == NB_FP32C || sys->prec == NB_FP32DS || sys->prec == NB_FP32DL;
   (void)ws_bytes;
   return NB_OK;
 }
@@ -401,6 +434,10 @@ int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, 
   hipError_t e;
   e = launch_update(P.a, update, s);  // also clears the pair kernel's work counter
   if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
+  if (P.a.nstiles) {
+    e = launch_sort(P.a, ctx->plan.B, s);
+    if (e != hipSuccess) return fail(NB_ERR_HIP, "sort kernel launch: %s", hipGetErrorString(e));
+  }
   int rc = pair(ctx, P, potmode, kick, s);
   if (rc || !ctx->plan.anysplit) return rc;
   e = launch_combine(P.a, potmode, kick, s);
@@ -451,11 +488,10 @@ int check_state(const Plan& p, const void* pos, const void* vel, const void* mas
 }
 
 void default_tiles(nbody_ctx* ctx) {
-  for (int f = 0; f < 3; ++f)
+  for (int f = 0; f < kFamilies; ++f)
     for (int c = 0; c < 3; ++c)
       ctx->tiles[f][c] = c == 0 ? TileCfg{1, 4, 128, 8, 0}
                        : f == FAM_F32 ? TileCfg{2, 4, 256, 4, 0}
-                       : f == FAM_DS  ? TileCfg{2, 4, 256, 8, 0}
                                       : TileCfg{2, 4, 256, 8, 0};
 }
 
@@ -659,7 +695,8 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   const long long nchunks = B + n / kChunk;
   const long long nitems = 8 * (B + n / 64);
   const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
-  return make_layout((int)B, n, (int)nchunks, nitems, npart).total;
+  const long long nstiles = B + n / kSortTile;  // the sort of NB_FP32DL
+  return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {
@@ -792,7 +829,7 @@ int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, con
 
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile) {
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
-  if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
+  if (prec < NB_FP32 || prec > NB_FP32DL) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
   if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
   TileCfg t{tile.k, tile.waves_per_group, tile.tile, tile.blocks_per_cu, tile.phased};
   const int fam = family_of(prec);
@@ -805,7 +842,7 @@ int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile
 
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile) {
   if (!ctx || !tile) return fail(NB_ERR_ARG, "NULL argument");
-  if (prec < NB_FP32 || prec > NB_FP64) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
+  if (prec < NB_FP32 || prec > NB_FP32DL) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
   if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
   const TileCfg& t = ctx->tiles[family_of(prec)][nclass];
   tile->k = t.k;

@@ -132,7 +132,7 @@ class HipExecutor:
         # (tile, waves) and its own tuned rest, so a job's result does not depend on the batch.
         if tile is None:
             from . import autotune
-            autotune.apply(self.ctx, fixed_tile={fam: SERVE_TILE for fam in ("f32", "ds", "f64")})
+            autotune.apply(self.ctx, fixed_tile={fam: SERVE_TILE for fam in ("f32", "ds", "f64", "dl")})
         else:
             for p in {prec, energy_prec}:
                 for ncl in range(3):

@@ -22,7 +22,7 @@ def _ragged_batch(seed=7, sizes=(1, 2, 3, 255, 256, 257, 700, 1000), field_every
     return inputs.concat(cl)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c", "fp32", "fp32dl"])
 def test_accel_single_cluster(prec):
     torch_dev()
     p, v, m = inputs.plummer(1000, 1234)
@@ -39,7 +39,7 @@ def test_accel_single_cluster(prec):
     assert np.all(np.isfinite(a))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c", "fp32dl"])
 def test_accel_ragged_batch_with_field(prec):
     torch_dev()
     b = _ragged_batch()
@@ -58,7 +58,7 @@ def test_accel_ragged_batch_with_field(prec):
             assert np.all(a[b.offsets[c]] == 0)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ds"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32dl"])
 def test_zero_softening_masks_self_term(prec):
     torch_dev()
     p, v, m = inputs.uniform_box(300, 9)
@@ -73,7 +73,7 @@ def test_zero_softening_masks_self_term(prec):
     assert np.abs(pot - rpot).max() <= (1e-13 if prec == "fp64" else 2e-6) * np.abs(rpot).max()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ds"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32dl"])
 def test_potential(prec):
     torch_dev()
     b = _ragged_batch(seed=3)
@@ -194,7 +194,7 @@ def test_full_size_c3_sampled_rows():
     one by one against the oracle, plus momentum conservation over all particles."""
     torch_dev()
     b = inputs.c3()
-    for prec in ("fp32ds", "fp32c", "fp64"):
+    for prec in ("fp32ds", "fp32c", "fp64", "fp32dl"):
         sim = make_sim(b, prec)
         a = sim.accel().cpu().numpy()
         rows = [(0, 64), (131072 - 32, 131072 + 32), (262144 - 64, 262144)]
@@ -218,7 +218,7 @@ def test_full_size_c2_sampled_rows_with_field():
     torch_dev()
     b = inputs.c2()
     rows = [(0, 64), (32768 - 32, 32768 + 32), (65536 - 64, 65536)]
-    for prec in ("fp64", "fp32ds", "fp32c"):
+    for prec in ("fp64", "fp32ds", "fp32c", "fp32dl"):
         sim = make_sim(b, prec)
         a = sim.accel().cpu().numpy()
         errs = []
@@ -243,7 +243,7 @@ def test_full_size_c4_sampled_clusters():
     order = np.argsort(sizes)
     pick = sorted(set([int(order[0]), int(order[-1])] + [int(order[np.searchsorted(sizes[order], n)])
                                                          for n in (1024, 2048, 4096, 9000)]))
-    for prec in ("fp32ds", "fp64"):
+    for prec in ("fp32ds", "fp64", "fp32dl"):
         sim = make_sim(b, prec)
         a = sim.accel().cpu().numpy()
         errs = []
@@ -283,7 +283,7 @@ def test_launch_shapes_agree(prec, tile):
         assert np.array_equal(sim.accel().cpu().numpy(), a)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32c", "fp32dl"])
 def test_equal_and_nearly_equal_masses(prec):
     """Clusters whose masses are all equal take the path that scales the mass-free sums by the
     common mass once; one different mass anywhere (first particle, last chunk, a split cluster)
@@ -306,7 +306,54 @@ def test_equal_and_nearly_equal_masses(prec):
     if prec in TOL:
         assert err.max() <= TOL[prec]
     assert np.median(err) <= TOL_MEDIAN[prec]
-    ptol = {"fp64": 1e-13, "fp32ds": 2e-6, "fp32c": 1e-5}[prec]
+    ptol = {"fp64": 1e-13, "fp32ds": 2e-6, "fp32c": 1e-5, "fp32dl": 2e-6}[prec]
     for c in range(b.B):
         s, e = b.offsets[c], b.offsets[c + 1]
         assert np.abs(pot[s:e] - rpot[s:e]).max() <= ptol * np.abs(rpot[s:e]).max(), c
+
+
+@pytest.mark.parametrize("tile", [(2, 4, 256, 4, 0), (2, 2, 256, 8, 0), (1, 4, 128, 8, 0), (2, 4, 128, 4, 0)])
+def test_local_mode_shapes_and_order(tile):
+    """The Morton-sorted local mode returns every particle's result at its own index and meets the
+    double-single bound in every compiled shape on a cluster large enough to have far tiles;
+    repeated evaluations are bitwise identical."""
+    torch_dev()
+    from paper_1003_3896_amd import nbody
+    p, v, m = inputs.plummer(20000, 4711)
+    b = inputs.single(p, v, m, 1e-3)
+    sim = make_sim(b, "fp32dl")
+    for ncl in range(3):
+        nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile)
+    a = sim.accel().cpu().numpy().copy()
+    assert np.array_equal(sim.accel().cpu().numpy(), a)
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    print("\n[fp32dl %s] %s" % (tile, stats(err)), flush=True)
+    assert err.max() <= TOL["fp32dl"]
+    assert np.median(err) <= TOL_MEDIAN["fp32dl"]
+    # blocks per CU (the grid) change nothing
+    for ncl in range(3):
+        nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile[:3], 2, 0)
+    assert np.array_equal(sim.accel().cpu().numpy(), a)
+
+
+def test_local_mode_alone_equals_in_batch():
+    """With one launch shape for every size class, a cluster's local-mode result (sort, item
+    boxes, near/far choices) is bitwise the same alone and in a ragged batch."""
+    torch_dev()
+    from paper_1003_3896_amd import nbody
+    b = _ragged_batch(seed=23, sizes=(5, 300, 2500, 9000, 17), field_every=2)
+
+    def run(batch):
+        sim = make_sim(batch, "fp32dl")
+        for ncl in range(3):
+            nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, 2, 4, 256, 4, 0)
+        return sim.accel().cpu().numpy().copy()
+
+    a1 = run(b)
+    ref, scale = oracle_reference(b)
+    assert rel_errors(a1, ref, scale).max() <= TOL["fp32dl"]
+    for c in (1, 2, 3):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        alone = inputs.single(b.pos[s:e], b.vel[s:e], b.mass[s:e], b.eps[c], bool(b.field[c]))
+        assert np.array_equal(run(alone), a1[s:e]), c
