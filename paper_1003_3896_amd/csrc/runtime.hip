@@ -292,9 +292,10 @@ void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p.cl[x].jlen > p.cl[y].jlen; });
   items.clear();
   const int tile = item_tile(t);
+  // j-range major: the blocks running at the same time stream the same sources through L2
   for (int b : order)
-    for (int i0 = 0; i0 < p.cl[b].n; i0 += tile)
-      for (int js = 0; js < p.cl[b].split; ++js) items.push_back(PairItem{b, i0, js, 0});
+    for (int js = 0; js < p.cl[b].split; ++js)
+      for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) items.push_back(PairItem{b, i0, js, 0});
 }
 
 Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
