@@ -59,10 +59,10 @@ def workload(name):
     from paper_1003_3896_amd import inputs
     if name == "c1":
         return inputs.c1(), "fp64"
-    # the fastest mode that meets the 1e-6 accuracy gate: the local double-single mode for the single
-    # large clusters, plain double-single for the ensemble of small ones
+    # the fastest mode that meets the 1e-6 accuracy gate over a whole step: the local double-single
+    # mode for the largest cluster, plain double-single where its sort costs more than it saves
     if name == "c2":
-        return inputs.c2(), "fp32dl"
+        return inputs.c2(), "fp32ds"
     if name == "c3":
         return inputs.c3(), "fp32dl"
     return inputs.c4(), "fp32ds"
@@ -436,7 +436,7 @@ def main():
 
     modes = {}
     if not args.no_modes and args.workload in ("c2", "c3"):
-        for m in (("fp32ds", "fp32c", "fp32", "fp64") if args.workload == "c3" else ("fp32ds", "fp64")):
+        for m in (("fp32ds", "fp32c", "fp32", "fp64") if args.workload == "c3" else ("fp32dl", "fp64")):
             if m == prec:
                 continue
             s2 = nbody.Simulation(batch, m)

@@ -106,8 +106,8 @@ void nbody_destroy(nbody_ctx* ctx);
  * nbody_last_error() says why): 8 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
  * about 2^21/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
- * 512..2^20 particles are split), plus 48 bytes per particle and 4 KiB per 2048 particles for
- * the sort of NB_FP32DL, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
+ * 512..2^20 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
+ * per cluster for the sort of NB_FP32DL, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
  * its contents are the library's between calls (the caller must not modify it while calls using
  * it are in flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);

@@ -1,59 +1,64 @@
 // O(N) kernels of libnbody for gfx950: fused kick + drift + centre-of-mass partials, and the
 // energy / momentum diagnostics.  All are HBM-bound; one block of kBlock threads
 // handles one chunk of kChunk particles of one cluster, so per-cluster reductions never mix
-// clusters.  Every reduction runs in a fixed order (bitwise reproducible); the last block of a
-// cluster to finish (device-scope atomic counter) combines the chunk partials and resets the
-// counter for the next launch.
+// clusters.  Every reduction runs in a fixed order (bitwise reproducible).  The update's chunk
+// partials are combined by a second kernel; the energy pass, which runs rarely, lets the last
+// block of a cluster to finish (device-scope atomic counter) combine them and reset the counter.
 #include "nb_device.h"
 
 namespace nb {
 
 enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3 };
 
-// Fixed-order tree reduction of V doubles per thread over the block; result valid in thread 0.
+// Fixed-order reduction of V doubles per thread over the block (a shuffle tree inside each wave,
+// then the waves in order); result valid in thread 0.  sh needs [V][kBlock / 64].
 template <int V>
 __device__ __forceinline__ void block_reduce(double (&val)[V], double (*sh)[kBlock]) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int q = 0; q < V; ++q) sh[q][t] = val[q];
+  for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+    for (int q = 0; q < V; ++q) val[q] += __shfl_down(val[q], m);
+  __syncthreads();  // sh is free (a previous reduction has been read)
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < V; ++q) sh[q][wave] = val[q];
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (t < s) {
+  if (t == 0)
 #pragma unroll
-      for (int q = 0; q < V; ++q) sh[q][t] += sh[q][t + s];
+    for (int q = 0; q < V; ++q) {
+      double s = sh[q][0];
+      for (int w = 1; w < kBlock / 64; ++w) s += sh[q][w];
+      val[q] = s;
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < V; ++q) val[q] = sh[q][0];
 }
 
-// Fixed-order tree reduction of V minima and V maxima per thread; result valid in thread 0.
+// Minima and maxima of V values per thread over the block; result valid in thread 0.
 template <int V>
 __device__ __forceinline__ void block_minmax(double (&mn)[V], double (&mx)[V], double (*sh)[kBlock]) {
-  const int t = threadIdx.x;
-  __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int q = 0; q < V; ++q) {
-    sh[q][t] = mn[q];
-    sh[V + q][t] = mx[q];
-  }
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (t < s) {
+  for (int m = 32; m >= 1; m >>= 1)
 #pragma unroll
-      for (int q = 0; q < V; ++q) {
-        sh[q][t] = fmin(sh[q][t], sh[q][t + s]);
-        sh[V + q][t] = fmax(sh[V + q][t], sh[V + q][t + s]);
-      }
+    for (int q = 0; q < V; ++q) {
+      mn[q] = fmin(mn[q], __shfl_down(mn[q], m));
+      mx[q] = fmax(mx[q], __shfl_down(mx[q], m));
     }
-    __syncthreads();
-  }
+  __syncthreads();
+  if (lane == 0)
 #pragma unroll
-  for (int q = 0; q < V; ++q) {
-    mn[q] = sh[q][0];
-    mx[q] = sh[V + q][0];
-  }
+    for (int q = 0; q < V; ++q) {
+      sh[q][wave] = mn[q];
+      sh[V + q][wave] = mx[q];
+    }
+  __syncthreads();
+  if (t == 0)
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+      for (int w = 1; w < kBlock / 64; ++w) {
+        mn[q] = fmin(mn[q], sh[q][w]);
+        mx[q] = fmax(mx[q], sh[V + q][w]);
+      }
 }
 
 // Returns true in every thread of the block that finished cluster `cl` last (after its partial
@@ -68,9 +73,10 @@ __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks)
   return last;
 }
 
-// Kick (v += kick_pre a) and drift (x += drift v) of one chunk (when `update`), then per cluster
-// the reference point ref = sum m x / sum m of the (new) positions, whether all masses are equal
-// (mconst = that mass, else 0) and the bounding box, combined in the last block of the cluster.
+// Kick (v += kick_pre a) and drift (x += drift v) of one chunk (when `update`), and the chunk's
+// partial sums for its cluster's reference point ref = sum m x / sum m of the (new) positions,
+// mass-uniformity flag and bounding box (combined by k_reduce: a kernel boundary rather than a
+// device-scope fence orders the two, a fence would write back the XCD's L2 in every block).
 // Always launched before the pair kernel, whose work counter it clears.
 constexpr int kPartials = 11;
 __global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
@@ -132,7 +138,14 @@ __global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
       p[8 + d] = mx[d];
     }
   }
-  if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
+}
+
+// One block per cluster: combines the chunk partials in a fixed order into the reference point,
+// the common mass (mconst = the mass when all are equal, else 0) and the bounding box.
+__global__ __launch_bounds__(kBlock) void k_reduce(Args a) {
+  __shared__ double sh[6][kBlock];
+  const DevCluster c = a.cl[blockIdx.x];
+  const int t = threadIdx.x;
   double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int q = t; q < c.nchunks; q += kBlock) {
@@ -143,20 +156,18 @@ __global__ __launch_bounds__(kBlock) void k_update(Args a, int update) {
       hi[d] = fmax(hi[d], p[8 + d]);
     }
   }
-  __syncthreads();
   block_reduce<5>(tot, sh);
   block_minmax<3>(lo, hi, sh);
   if (t == 0) {
     const double M = tot[3];
-    a.ref[ch.cluster] = M > 0.0 ? make_double4(tot[0] / M, tot[1] / M, tot[2] / M, M)
+    a.ref[blockIdx.x] = M > 0.0 ? make_double4(tot[0] / M, tot[1] / M, tot[2] / M, M)
                                 : make_double4(0.0, 0.0, 0.0, 0.0);
-    a.mconst[ch.cluster] = tot[4] == 0.0 ? a.mass[c.off] : 0.0;
-    double* b = a.box + 6 * (size_t)ch.cluster;
+    a.mconst[blockIdx.x] = tot[4] == 0.0 ? a.mass[c.off] : 0.0;
+    double* b = a.box + 6 * (size_t)blockIdx.x;
     for (int d = 0; d < 3; ++d) {
       b[d] = lo[d];
       b[3 + d] = hi[d];
     }
-    a.chunk_counter[ch.cluster] = 0;
   }
 }
 
@@ -266,8 +277,9 @@ hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_update(const Args& a, bool update, hipStream_t s) {
+hipError_t launch_update(const Args& a, int B, bool update, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(a.nchunks), dim3(kBlock), 0, s, a, update ? 1 : 0);
+  hipLaunchKernelGGL(k_reduce, dim3(B), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

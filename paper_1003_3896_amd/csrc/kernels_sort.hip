@@ -61,56 +61,35 @@ __global__ __launch_bounds__(kBlock) void k_rhist(Args a, int src, int shift) {
   for (int d = threadIdx.x; d < kRadix; d += kBlock) out[d] = h[d];
 }
 
-// Per cluster (one block): turns the digit counts of its sort tiles into each tile's first
-// destination per digit: all smaller digits of the cluster, then the same digit in earlier tiles.
-constexpr int kDigitsPerThread = kRadix / kBlock;
-__global__ __launch_bounds__(kBlock) void k_rscan(Args a) {
+// Per cluster (one block, one thread per digit): each tile's count of a digit becomes the number
+// of that digit in the cluster's earlier tiles, and sbase[cluster][digit] the number of smaller
+// digits in the whole cluster; their sum is the tile's first destination for the digit.
+__global__ __launch_bounds__(kRadix) void k_rscan(Args a) {
   const DevCluster c = a.cl[blockIdx.x];
-  const int t = threadIdx.x;
-  int run[kDigitsPerThread];
-#pragma unroll
-  for (int r = 0; r < kDigitsPerThread; ++r) run[r] = 0;
-  // exclusive prefix over the tiles, digit by digit (loads batched to overlap their latency)
-  constexpr int kBatch = 8;
+  const int d = threadIdx.x;
+  int run = 0;
+  constexpr int kBatch = 16;  // loads in flight per thread
   for (int q0 = 0; q0 < c.nstiles; q0 += kBatch) {
-    int v[kBatch][kDigitsPerThread];
+    int v[kBatch];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b)
+    for (int b = 0; b < kBatch; ++b) v[b] = q0 + b < c.nstiles ? a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + d] : 0;
 #pragma unroll
-      for (int r = 0; r < kDigitsPerThread; ++r)
-        v[b][r] = q0 + b < c.nstiles ? a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] : 0;
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-      for (int r = 0; r < kDigitsPerThread; ++r) {
-        if (q0 + b < c.nstiles) a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] = run[r];
-        run[r] += v[b][r];
-      }
+    for (int b = 0; b < kBatch; ++b) {
+      if (q0 + b < c.nstiles) a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + d] = run;
+      run += v[b];
+    }
   }
-  // exclusive prefix over the digits: within the thread, then across threads (fixed-order scan)
-  __shared__ int sum[kBlock];
-  int pre[kDigitsPerThread], tot = 0;
-#pragma unroll
-  for (int r = 0; r < kDigitsPerThread; ++r) {
-    pre[r] = tot;
-    tot += run[r];
-  }
-  sum[t] = tot;
+  // exclusive prefix over the digits (fixed-order Hillis-Steele scan)
+  __shared__ int sum[kRadix];
+  sum[d] = run;
   __syncthreads();
-  for (int s = 1; s < kBlock; s <<= 1) {
-    const int x = t >= s ? sum[t - s] : 0;
+  for (int s = 1; s < kRadix; s <<= 1) {
+    const int x = d >= s ? sum[d - s] : 0;
     __syncthreads();
-    sum[t] += x;
+    sum[d] += x;
     __syncthreads();
   }
-  const int base_t = sum[t] - tot;
-  for (int q0 = 0; q0 < c.nstiles; q0 += kBatch) {
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-      for (int r = 0; r < kDigitsPerThread; ++r)
-        if (q0 + b < c.nstiles) a.shist[(size_t)(c.stile0 + q0 + b) * kRadix + kDigitsPerThread * t + r] += base_t + pre[r];
-  }
+  a.sbase[(size_t)blockIdx.x * kRadix + d] = sum[d] - run;
 }
 
 // Stable scatter of one sort tile: elements are ranked in tile order, 256 per round; inside a
@@ -121,7 +100,8 @@ __global__ __launch_bounds__(kBlock) void k_rscatter(Args a, int src, int shift)
   const Chunk st = a.stiles[blockIdx.x];
   const long long base = a.cl[st.cluster].off;
   const int* offs = a.shist + (size_t)blockIdx.x * kRadix;
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) dst[d] = offs[d];
+  const int* cbase = a.sbase + (size_t)st.cluster * kRadix;
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) dst[d] = offs[d] + cbase[d];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int r0 = 0; r0 < st.count; r0 += kBlock) {
@@ -175,7 +155,7 @@ hipError_t launch_sort(const Args& a, int B, hipStream_t s) {
   int src = 0;
   for (int shift = 0; shift < 3 * kRadixBits; shift += kRadixBits) {
     hipLaunchKernelGGL(k_rhist, dim3(a.nstiles), dim3(kBlock), 0, s, a, src, shift);
-    hipLaunchKernelGGL(k_rscan, dim3(B), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rscan, dim3(B), dim3(kRadix), 0, s, a);
     hipLaunchKernelGGL(k_rscatter, dim3(a.nstiles), dim3(kBlock), 0, s, a, src, shift);
     src ^= 1;
   }

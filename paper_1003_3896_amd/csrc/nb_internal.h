@@ -70,7 +70,8 @@ struct Args {
   int nstiles;
   unsigned* skey[2];
   int* sval[2];
-  int* shist;          // [nstiles][kRadix]
+  int* shist;          // [nstiles][kRadix] digit counts, then each tile's offsets within the digit
+  int* sbase;          // [B][kRadix] first destination of each digit in its cluster
   const int* perm;     // null: particles in their own order
   double4* spos;       // [Ntot] (x, y, z, m) in sorted order (NB_FP32DL), else null
   double* mconst;      // [B] the common mass of a cluster whose masses are all equal, else 0
@@ -100,7 +101,7 @@ struct TileCfg {
 };
 
 // Launchers (kernels_*.hip).  All return hipSuccess or the launch error.
-hipError_t launch_update(const Args& a, bool update, hipStream_t s);
+hipError_t launch_update(const Args& a, int B, bool update, hipStream_t s);
 
 hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, bool potmode, bool kick,
                        hipStream_t s);

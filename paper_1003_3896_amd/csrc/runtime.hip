@@ -61,7 +61,7 @@ const Sym6 kSym6;
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
   size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, part, skey, sval, shist,
-      spos, total;
+      sbase, spos, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -226,6 +226,8 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + (nstiles ? sizeof(int) * 2 * (size_t)ntot : 0));
   L.shist = o;  // [nstiles][kRadix]
   o = align_up(o + sizeof(int) * (size_t)nstiles * kRadix);
+  L.sbase = o;  // [B][kRadix]
+  o = align_up(o + (nstiles ? sizeof(int) * (size_t)B * kRadix : 0));
   L.spos = o;  // [ntot] sorted (x, y, z, m)
   o = align_up(o + (nstiles ? sizeof(double4) * (size_t)ntot : 0));
   L.total = o;
@@ -381,6 +383,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.sval[0] = reinterpret_cast<int*>(w + L.sval);
   a.sval[1] = a.sval[0] + p.ntot;
   a.shist = reinterpret_cast<int*>(w + L.shist);
+  a.sbase = reinterpret_cast<int*>(w + L.sbase);
   a.perm = p.nstiles ? a.sval[1] : nullptr;
   a.spos = p.nstiles ? reinterpret_cast<double4*>(w + L.spos) : nullptr;
   a.mconst = reinterpret_cast<double*>(w + L.mconst);
@@ -433,7 +436,7 @@ int pair(nbody_ctx* ctx, const Prepared& P, bool potmode, bool kick, hipStream_t
 // counter) -> pair -> [combine of split clusters].
 int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, hipStream_t s) {
   hipError_t e;
-  e = launch_update(P.a, update, s);  // also clears the pair kernel's work counter
+  e = launch_update(P.a, ctx->plan.B, update, s);  // also clears the pair kernel's work counter
   if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
   if (P.a.nstiles) {
     e = launch_sort(P.a, ctx->plan.B, s);
