@@ -283,8 +283,8 @@ __device__ __forceinline__ void full_tile_terms(const LDS& sh, int u0, int j0, c
 // PH: full tiles in phases of 8 pair terms (all coordinate differences and r^2, then the 8
 // v_rsq_f32 back to back, then the products and sums), fenced against compiler reordering, so the
 // transcendental ops of the waves sharing a SIMD can issue in pairs.
-template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT, bool PH = false>
-__global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
+template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT, bool PH>
+__device__ __forceinline__ void pair32_items(const Args& a, int kick) {
   static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
   constexpr bool LOC = FAM == FAM_DL;         // local centring + near/far tiles
   constexpr bool DS = FAM == FAM_DS || LOC;  // double-single records and i-particles
@@ -453,6 +453,18 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
   }
 }
 
+template <int FAM, int K, int W, int T, bool FOLD, bool MASK, bool POT, bool PH = false>
+__global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
+  pair32_items<FAM, K, W, T, FOLD, MASK, POT, PH>(a, kick);
+}
+
+// The local family keeps 4 waves per SIMD (at most 128 VGPRs): with both loops in one kernel the
+// compiler would otherwise settle on 3, and the extra wave hides more of the FP32 chain's latency.
+template <int K, int W, int T, bool MASK, bool POT>
+__global__ __launch_bounds__(kBlock, 4) void k_pair32_local(Args a, int kick) {
+  pair32_items<FAM_DL, K, W, T, true, MASK, POT, false>(a, kick);
+}
+
 // ---------------------------------------------------------------------------------------------
 // FP64 family
 
@@ -547,7 +559,10 @@ PairFn pair_flags(bool fold, bool mask, bool pot) {
   if constexpr (FAM == FAM_F64) {
     if (mask) return pot ? k_pair64<K, W, T, true, true> : k_pair64<K, W, T, true, false>;
     return pot ? k_pair64<K, W, T, false, true> : k_pair64<K, W, T, false, false>;
-  } else if constexpr (FAM == FAM_DS || FAM == FAM_DL) {
+  } else if constexpr (FAM == FAM_DL) {
+    if (mask) return pot ? k_pair32_local<K, W, T, true, true> : k_pair32_local<K, W, T, true, false>;
+    return pot ? k_pair32_local<K, W, T, false, true> : k_pair32_local<K, W, T, false, false>;
+  } else if constexpr (FAM == FAM_DS) {
     if (mask) return pot ? k_pair32<FAM, K, W, T, true, true, true> : k_pair32<FAM, K, W, T, true, true, false>;
     return pot ? k_pair32<FAM, K, W, T, true, false, true> : k_pair32<FAM, K, W, T, true, false, false>;
   } else {
