@@ -26,7 +26,8 @@ def _same(a, b):
             and np.array_equal(a.acc.cpu().numpy(), b.acc.cpu().numpy()))
 
 
-@pytest.mark.parametrize("integ,prec", [("leapfrog", "fp64"), ("sym6", "fp32ds"), ("leapfrog", "fp32")])
+@pytest.mark.parametrize("integ,prec", [("leapfrog", "fp64"), ("sym6", "fp32ds"), ("leapfrog", "fp32"),
+                                        ("sym6", "fp32dl")])
 def test_graph_replays_match_eager(integ, prec):
     torch = torch_dev()
     cl = []

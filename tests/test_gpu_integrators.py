@@ -21,7 +21,7 @@ def _batch():
     return inputs.concat(cl)
 
 
-@pytest.mark.parametrize("prec", ["fp32ds", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32ds", "fp64", "fp32dl"])
 def test_substeps_equal_repeated_substep(prec):
     """Chained rounds (captured into a graph and replayed with a new coefficient table each call)
     equal single eager substeps, call after call, with other work in between."""
@@ -46,14 +46,17 @@ def test_substeps_equal_repeated_substep(prec):
         torch.cuda.synchronize()
 
 
-def test_step_functions_equal_their_substep_sequences():
+@pytest.mark.parametrize("prec", ["fp32ds", "fp32dl"])
+def test_step_functions_equal_their_substep_sequences(prec):
+    """The step functions equal their stage sequences bitwise; in the local mode this also shows
+    that the per-evaluation sort makes every result a function of the state alone."""
     torch = torch_dev()
     b = _batch()
     dt = 1.0 / 700
     d, k = nbody.nbody_sym6_coefficients()
     for integ in ("leapfrog", "sym6"):
-        s1 = nbody.Simulation(b, "fp32ds")
-        s2 = nbody.Simulation(b, "fp32ds")
+        s1 = nbody.Simulation(b, prec)
+        s2 = nbody.Simulation(b, prec)
         nbody.nbody_use_graphs(s1.ctx, False)
         s1.accel()
         s2.accel()
@@ -80,7 +83,7 @@ def test_c2_like_sym6_with_field_follows_oracle():
     a0 = oracle.total_accel(b.pos, b.mass, 1.0, 1e-4, True)
     rp, rv, _ = oracle.step(b.pos, b.vel, b.mass, a0, dt, 6, "sym6", 1.0, 1e-4, True)
     de_ref = abs(oracle.energy(rp, rv, b.mass, 1.0, 1e-4, True)[3] - e0[3]) / abs(e0[3])
-    for prec, tol in (("fp64", 1e-10), ("fp32ds", 1e-7)):
+    for prec, tol in (("fp64", 1e-10), ("fp32ds", 1e-7), ("fp32dl", 1e-7)):
         s = nbody.Simulation(b, prec)
         s.accel()
         s.step("sym6", dt, 6)
