@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "paper"])
+    ap.add_argument("--sizes", default=None, help="paper: comma-separated N (default 480*2^k .. 1,536,000)")
     ap.add_argument("--jobs", type=int, default=120, help="c5: jobs in the open-loop stream")
     ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
@@ -372,6 +373,70 @@ def bench_c5(args):
     }
 
 
+def bench_paper(args):
+    """The paper's timing set-up (Sect. 5): a uniform sphere with virial ratio 0.3, softening
+    0.005 R / N^(1/3), in the galaxy, leapfrog steps of 5e-4, for N = 480 * 2^k up to 1,536,000:
+    time per step and pair interactions per second at every N (the analog of its timing curves)."""
+    import numpy as np
+    import torch
+    from paper_1003_3896_amd import inputs, nbody
+    torch.cuda.set_device(0)
+    prec = args.prec or "fp32dl"
+    sizes = [int(x) for x in args.sizes.split(",")] if args.sizes else inputs.PAPER_SIZES
+    scan = []
+    last = None
+    for n in sizes:
+        batch = inputs.paper_timing(n)
+        sim = nbody.Simulation(batch, prec)
+        steps = max(1, min(args.steps, int(2e12 / max(n * n, 1))))  # about a second of pair work each
+        wall, kms, nl = time_steps(sim, "leapfrog", batch.meta["dt"], steps, 1, torch)
+        row = {"n": n, "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4),
+               "G_interactions_per_s": round(n * n * steps / wall / 1e9, 3),
+               "pair_kernel_ms": round(kms / max(nl, 1), 4)}
+        print("paper N=%d %s" % (n, row), file=sys.stderr, flush=True)
+        scan.append(row)
+        if n == sizes[-1]:
+            last = (batch, sim.pos.cpu().numpy(), sim.acc.cpu().numpy(), row, wall, steps)
+        sim.close()
+    batch, pos_final, a_gpu, row, wall, steps = last
+    pair_ms = row["pair_kernel_ms"]
+    achieved = FLOPS_PER_INTERACTION * row["n"] ** 2 / (pair_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+    result = {
+        "metric": METRIC,
+        "value": row["G_interactions_per_s"],
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": row["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic (seeded uniform spheres)",
+        "config": {"workload": "uniform sphere, virial ratio 0.3, eps = 0.005/N^(1/3), galaxy field, leapfrog "
+                               "dt = 5e-4; N = %d..%d" % (sizes[0], sizes[-1]),
+                   "precision_mode": prec, "value_at_n": row["n"]},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": "pair (%s)" % prec,
+                     "kernel_ms": pair_ms, "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "scan": scan,
+    }
+    # the paper's own figure for this workload and N (one Tesla C1060, Table 3 at 20 flops per
+    # interaction): another machine's number, reported as context
+    paper = {"fp64": 22.0 / 20}.get(prec, 423.0 / 20)  # G interactions/s
+    if row["n"] == 1536000:
+        result["vs_baseline"] = round(row["G_interactions_per_s"] / paper, 2)
+        result["vs_baseline_basis"] = ("the paper's single-GPU %s figure for N = 1,536,000 (%.1f G interactions/s, "
+                                       "Tesla C1060); other hardware" % ("FP64" if prec == "fp64" else "FP32", paper))
+    if not args.no_cpu_baseline:
+        cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
+        result["cpu_baseline"] = cb
+        result["parity_sample"] = parity
+    return result
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +445,9 @@ def main():
         sys.exit(2)
     if args.workload == "c5":
         print(json.dumps(bench_c5(args)), flush=True)
+        return
+    if args.workload == "paper":
+        print(json.dumps(bench_paper(args)), flush=True)
         return
     import torch
     from paper_1003_3896_amd import inputs, nbody

@@ -94,6 +94,42 @@ def plummer(n: int, seed: int, masses: Optional[np.ndarray] = None, a: float = P
     return np.ascontiguousarray(pos), np.ascontiguousarray(vel), np.ascontiguousarray(mass)
 
 
+def uniform_sphere(n: int, seed: int, q: float = 0.3, R: float = 1.0, G: float = 1.0, M: float = 1.0):
+    """Equal-mass particles uniform in a sphere of radius R, velocities isotropic with speeds
+    uniform in [0, 1), rescaled so that the virial ratio 2K/|W| equals q (Sect. 3's set-up).
+
+    The potential energy of the rescaling is the continuum value W = -3 G M^2 / (5 R) of a uniform
+    sphere (a closed form, not a pair sum).  Draw order: radii, position directions, speeds,
+    velocity directions.  Centre of mass at rest at the origin.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    rng = _rng(seed)
+    r = R * rng.uniform(0.0, 1.0, n) ** (1.0 / 3.0)
+    pos = _isotropic(rng, r)
+    vel = _isotropic(rng, rng.uniform(0.0, 1.0, n))
+    mass = np.full(n, M / n)
+    pos -= pos.mean(axis=0)
+    vel -= vel.mean(axis=0)
+    k = 0.5 * (mass[:, None] * vel * vel).sum()
+    k_target = 0.5 * q * 0.6 * G * M * M / R
+    if k > 0.0:
+        vel *= math.sqrt(k_target / k)
+    return np.ascontiguousarray(pos), np.ascontiguousarray(vel), mass
+
+
+def paper_timing(n: int, seed: int = 7000):
+    """The timing set-up of Sect. 5: the uniform sphere with q = 0.3, eps = 0.005 R / N^(1/3), on a
+    circular orbit in the galaxy, leapfrog with dt = 5e-4 crossing times (seed 7000 + n)."""
+    p, v, m = uniform_sphere(n, seed + n)
+    p, v = on_orbit(p, v)
+    return single(p, v, m, 0.005 / n ** (1.0 / 3.0), True, name="uniform-sphere-q0.3-%d" % n,
+                  integrator="leapfrog", steps=1000, dt=5e-4)
+
+
+PAPER_SIZES = [480 * 2 ** k for k in range(12)] + [1536000]  # 480 .. 983040, then 1,536,000
+
+
 def uniform_box(n: int, seed: int, scale: float = 1.0, mass_range=(0.5, 1.5)):
     """Uniform random positions in a cube, random masses: generic parity-test input."""
     rng = _rng(seed)
