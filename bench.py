@@ -38,7 +38,8 @@ METRIC = "G pair-interactions/s & %FP32 VALU peak; batched p50/p99 job latency"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's own step count; C3 1000, C2 200, C1 and C4 100)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "paper"])
     ap.add_argument("--sizes", default=None, help="paper: comma-separated N (default 480*2^k .. 1,536,000)")
@@ -388,7 +389,7 @@ def bench_paper(args):
     for n in sizes:
         batch = inputs.paper_timing(n)
         sim = nbody.Simulation(batch, prec)
-        steps = max(1, min(args.steps, int(2e12 / max(n * n, 1))))  # about a second of pair work each
+        steps = max(1, min(args.steps or 30, int(2e12 / max(n * n, 1))))  # about a second of pair work each
         wall, kms, nl = time_steps(sim, "leapfrog", batch.meta["dt"], steps, 1, torch)
         row = {"n": n, "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4),
                "G_interactions_per_s": round(n * n * steps / wall / 1e9, 3),
@@ -455,6 +456,8 @@ def main():
     torch.cuda.set_device(0)
     batch, prec = workload(args.workload)
     prec = args.prec or prec
+    if args.steps is None:
+        args.steps = int(batch.meta["steps"])
     integrator = batch.meta["integrator"]
     dt = batch.meta["dt"]
     evals_per_step = 1 if integrator == "leapfrog" else 7
@@ -575,7 +578,7 @@ def main():
         result["accel_error_initial_state"] = mode_errors(batch, accel_init, nrows)
         if args.workload in ("c2", "c3"):
             result["accel_error_on_fp64_trajectory"] = sampled_state_errors(
-                batch, list(accel_init), integrator, dt, args.steps, nrows, torch)
+                batch, list(accel_init), integrator, dt, min(args.steps, 100), nrows, torch)
     print(json.dumps(result), flush=True)
 
 
