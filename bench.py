@@ -41,8 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's own step count; C3 1000, C2 200, C1 and C4 100)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "paper"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "paper", "bh"])
     ap.add_argument("--sizes", default=None, help="paper: comma-separated N (default 480*2^k .. 1,536,000)")
+    ap.add_argument("--ratios", default=None, help="bh: comma-separated black-hole to cluster mass ratios")
     ap.add_argument("--jobs", type=int, default=120, help="c5: jobs in the open-loop stream")
     ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
@@ -438,6 +439,65 @@ def bench_paper(args):
     return result
 
 
+def bench_black_hole(args):
+    """The stiff collisions of Sect. 6.2 (Table 8): an N = 15360 uniform sphere falling through a
+    central point mass of 0.1, 1, 50 and 105 cluster masses from (10, 0, 0), sym6 with dt = 1e-4;
+    energy and angular-momentum changes (FP64 diagnostics) after the given number of steps (the
+    paper's runs are 4e4 steps, t = [0, 4]; the default here covers the first 4000)."""
+    import numpy as np
+    import torch
+    from paper_1003_3896_amd import inputs, nbody
+    torch.cuda.set_device(0)
+    prec = args.prec or "fp32ds"
+    steps = args.steps or 4000
+    rows, tot_int, tot_wall = [], 0.0, 0.0
+    ratios = [float(x) for x in args.ratios.split(",")] if args.ratios else inputs.BH_RATIOS
+    for ratio in ratios:
+        b = inputs.paper_black_hole(ratio)
+        sim = nbody.Simulation(b, prec)
+        e0 = sim.energy(prec="fp64")[0].cpu().numpy().copy()
+        sim.accel()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:  # in slices, so a long run prints its progress
+            k = min(2000, steps - done)
+            sim.step("sym6", b.meta["dt"], k)
+            torch.cuda.synchronize()
+            done += k
+            print("bh ratio %g: %d / %d steps" % (ratio, done, steps), file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        e1 = sim.energy(prec="fp64")[0].cpu().numpy().copy()
+        L0, L1 = e0[7:10], e1[7:10]
+        row = {"mbh_over_m": ratio, "steps": steps, "t_end": round(steps * b.meta["dt"], 6),
+               "dE_over_E0": float(abs(e1[3] - e0[3]) / abs(e0[3])),
+               "dL_over_L0": float(np.linalg.norm(L1 - L0) / np.linalg.norm(L0)),
+               "dLz_over_Lz0": float(abs(L1[2] - L0[2]) / abs(L0[2])),
+               "ms_per_step": round(wall / steps * 1e3, 4), "finite": bool(e1[15] == 0)}
+        rows.append(row)
+        tot_int += b.interactions_per_eval() * 7 * steps
+        tot_wall += wall
+        sim.close()
+    return {
+        "metric": METRIC,
+        "value": round(tot_int / tot_wall / 1e9, 3),
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(tot_wall / (steps * len(rows)) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic (seeded uniform sphere)",
+        "config": {"workload": "cluster-black hole collisions: N = 15360 uniform sphere, virial ratio 0.3, "
+                               "from (10, 0, 0) at 0.001 v_c, black hole of 0.1/1/50/105 cluster masses, "
+                               "sym6 dt = 1e-4", "precision_mode": prec},
+        "table8": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -449,6 +509,9 @@ def main():
         return
     if args.workload == "paper":
         print(json.dumps(bench_paper(args)), flush=True)
+        return
+    if args.workload == "bh":
+        print(json.dumps(bench_black_hole(args)), flush=True)
         return
     import torch
     from paper_1003_3896_amd import inputs, nbody

@@ -75,12 +75,17 @@ enum {
 enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3, NB_FP32DL = 4 };
 
 /* External galaxy (Eq. 3, F_ext), G-scaled except for the halo:
- *   Hernquist bulge      Phi_b = -G Mb / (r + ab)
- *   Miyamoto-Nagai disk  Phi_d = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
- *   logarithmic halo     Phi_h = vh^2 / 2 ln(r^2 + dh^2)
- * with R^2 = x^2 + y^2 and r^2 = R^2 + z^2; a_ext = -grad(Phi_b + Phi_d + Phi_h). */
+ *   Hernquist bulge      Phi_b  = -G Mb / (r + ab)
+ *   Miyamoto-Nagai disk  Phi_d  = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
+ *   logarithmic halo     Phi_h  = vh^2 / 2 ln(r^2 + dh^2)
+ *   central black hole   Phi_bh = -G Mbh / sqrt(r^2 + ebh^2)   (Sect. 6.2: a massive point fixed
+ *                        at the galaxy centre; Mbh = 0 leaves it out)
+ * with R^2 = x^2 + y^2 and r^2 = R^2 + z^2; a_ext = -grad(Phi_b + Phi_d + Phi_h + Phi_bh).
+ * Mbh > 0 with ebh = 0 is singular at the origin (a particle exactly there gets a non-finite
+ * acceleration, which the energy diagnostics flag). */
 typedef struct {
   double Mb, ab, Md, ad, bd, vh, dh;
+  double Mbh, ebh;
 } nbody_galaxy;
 
 /* A ragged batch of clusters.  All pointers are HOST pointers read during the call only. */

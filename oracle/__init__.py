@@ -101,7 +101,10 @@ def _p(a):
 
 
 def _gal(galaxy):
-    return _f64(GALAXY if galaxy is None else galaxy)
+    """Galaxy parameters as the C side reads them: (Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh); a
+    7-tuple has no central black hole."""
+    g = list(GALAXY if galaxy is None else galaxy)
+    return _f64(g + [0.0] * (9 - len(g)))
 
 
 def num_threads() -> int:

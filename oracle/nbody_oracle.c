@@ -108,15 +108,18 @@ void oracle_accel(int64_t n, const double* pos, const double* mass, double G, do
 }
 
 /*
- * External galactic field.  gal = {Mb, ab, Md, ad, bd, vh, dh}.
+ * External galactic field.  gal = {Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh}.
  *   Hernquist bulge:      Phi_b = -G Mb / (r + ab)
  *   Miyamoto-Nagai disk:  Phi_d = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
  *   logarithmic halo:     Phi_h =  vh^2 / 2 * ln(r^2 + dh^2)
+ *   central black hole:   Phi_bh = -G Mbh / sqrt(r^2 + ebh^2)  (a fixed point mass at the galaxy
+ *                         centre, softened like a star; the massive point of Sect. 6.2)
  * with R^2 = x^2 + y^2, r^2 = R^2 + z^2.  Acceleration is -grad Phi, written out per component.
  * acc/phi may be NULL.
  */
 static void ext_one(const double* x, double G, const double* gal, double* a, double* phi) {
   const double Mb = gal[0], ab = gal[1], Md = gal[2], ad = gal[3], bd = gal[4], vh = gal[5], dh = gal[6];
+  const double Mbh = gal[7], ebh = gal[8];
   const double X = x[0], Y = x[1], Z = x[2];
   const double R2 = X * X + Y * Y;
   const double r2 = R2 + Z * Z;
@@ -134,16 +137,20 @@ static void ext_one(const double* x, double G, const double* gal, double* a, dou
   const double gdz = G * Md * As / (D3 * s);  /* d Phi_d / dz = gdz * z */
   /* halo */
   const double gh = vh * vh / (r2 + dh * dh); /* d Phi_h / dx = gh * x */
+  /* black hole: d Phi_bh / dx = G Mbh x / (r^2 + ebh^2)^(3/2) */
+  const double q2 = r2 + ebh * ebh;
+  const double gbh = Mbh > 0.0 ? G * Mbh / (q2 * sqrt(q2)) : 0.0;
   if (a) {
-    a[0] = -(gb * X + gdR * X + gh * X);
-    a[1] = -(gb * Y + gdR * Y + gh * Y);
-    a[2] = -(gb * Z + gdz * Z + gh * Z);
+    a[0] = -(gb * X + gdR * X + gh * X + gbh * X);
+    a[1] = -(gb * Y + gdR * Y + gh * Y + gbh * Y);
+    a[2] = -(gb * Z + gdz * Z + gh * Z + gbh * Z);
   }
   if (phi) {
     const double pb = -G * Mb / (r + ab);
     const double pd = -G * Md / D;
     const double ph = 0.5 * vh * vh * log(r2 + dh * dh);
-    *phi = pb + pd + ph;
+    const double pbh = Mbh > 0.0 ? -G * Mbh / sqrt(q2) : 0.0;
+    *phi = pb + pd + ph + pbh;
   }
 }
 

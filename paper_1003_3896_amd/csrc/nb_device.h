@@ -5,7 +5,8 @@
 namespace nb {
 
 // External galaxy field at (X,Y,Z) in FP64 (the F_ext term of Eq. 3):
-// Hernquist bulge + Miyamoto-Nagai disk + logarithmic halo; acceleration = -grad Phi.
+// Hernquist bulge + Miyamoto-Nagai disk + logarithmic halo + an optional softened point mass at the
+// centre (the black hole of Sect. 6.2); acceleration = -grad Phi.
 __device__ __forceinline__ void galaxy_accel(const Galaxy& g, double G, double X, double Y, double Z, double& ax,
                                              double& ay, double& az) {
   const double R2 = X * X + Y * Y;
@@ -19,10 +20,12 @@ __device__ __forceinline__ void galaxy_accel(const Galaxy& g, double G, double X
   const double fd = G * g.Md / (D2 * sqrt(D2));                // (1/R) dPhi_d/dR
   const double fz = fd * as / zs;                               // (1/z) dPhi_d/dz
   const double fh = g.vh * g.vh / (r2 + g.dh * g.dh);           // (1/r) dPhi_h/dr
-  const double fxy = fb + fd + fh;
+  const double q2 = r2 + g.ebh * g.ebh;
+  const double fbh = g.Mbh > 0.0 ? G * g.Mbh / (q2 * sqrt(q2)) : 0.0;  // (1/r) dPhi_bh/dr
+  const double fxy = fb + fd + fh + fbh;
   ax = -fxy * X;
   ay = -fxy * Y;
-  az = -(fb + fz + fh) * Z;
+  az = -(fb + fz + fh + fbh) * Z;
 }
 
 __device__ __forceinline__ double galaxy_potential(const Galaxy& g, double G, double X, double Y, double Z) {
@@ -31,7 +34,8 @@ __device__ __forceinline__ double galaxy_potential(const Galaxy& g, double G, do
   const double r = sqrt(r2);
   const double zs = sqrt(Z * Z + g.bd * g.bd);
   const double as = g.ad + zs;
-  return -G * g.Mb / (r + g.ab) - G * g.Md / sqrt(R2 + as * as) + 0.5 * g.vh * g.vh * log(r2 + g.dh * g.dh);
+  const double pbh = g.Mbh > 0.0 ? -G * g.Mbh / sqrt(r2 + g.ebh * g.ebh) : 0.0;
+  return -G * g.Mb / (r + g.ab) - G * g.Md / sqrt(R2 + as * as) + 0.5 * g.vh * g.vh * log(r2 + g.dh * g.dh) + pbh;
 }
 
 // 1/sqrt(x) in FP64: the hardware estimate (relative error ~2^-24) refined by one

@@ -49,7 +49,7 @@ struct PairItem {
 };
 
 struct Galaxy {
-  double Mb, ab, Md, ad, bd, vh, dh;
+  double Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh;
 };
 
 // Everything the kernels of one call need; passed by value.

@@ -180,11 +180,11 @@ int check_system(const nbody_system* sys) {
     for (int b = 0; b < sys->nclusters; ++b) anyfield |= sys->field[b] != 0;
   if (anyfield) {
     const nbody_galaxy& g = sys->galaxy;
-    const double v[7] = {g.Mb, g.ab, g.Md, g.ad, g.bd, g.vh, g.dh};
+    const double v[9] = {g.Mb, g.ab, g.Md, g.ad, g.bd, g.vh, g.dh, g.Mbh, g.ebh};
     for (double x : v)
       if (!std::isfinite(x)) return fail(NB_ERR_ARG, "galaxy parameters must be finite");
-    if (g.Mb < 0 || g.Md < 0 || g.ad < 0 || g.vh < 0)
-      return fail(NB_ERR_ARG, "galaxy masses, ad and vh must be >= 0");
+    if (g.Mb < 0 || g.Md < 0 || g.ad < 0 || g.vh < 0 || g.Mbh < 0 || g.ebh < 0)
+      return fail(NB_ERR_ARG, "galaxy masses, ad, vh and ebh must be >= 0");
     if (!(g.ab > 0 && g.bd > 0 && g.dh > 0)) return fail(NB_ERR_ARG, "galaxy ab, bd and dh must be > 0");
   }
   return NB_OK;
@@ -393,8 +393,8 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.part = reinterpret_cast<double4*>(w + L.part);
   a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
   a.G = sys->G;
-  a.gal = Galaxy{sys->galaxy.Mb, sys->galaxy.ab, sys->galaxy.Md, sys->galaxy.ad,
-                 sys->galaxy.bd, sys->galaxy.vh, sys->galaxy.dh};
+  a.gal = Galaxy{sys->galaxy.Mb, sys->galaxy.ab, sys->galaxy.Md, sys->galaxy.ad, sys->galaxy.bd,
+                 sys->galaxy.vh, sys->galaxy.dh, sys->galaxy.Mbh, sys->galaxy.ebh};
   a.prec = sys->prec;
   P.tile = t;
   P.grid = std::max(1, std::min(a.nitems, ctx->cus * t.bpc));

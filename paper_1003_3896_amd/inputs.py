@@ -30,6 +30,7 @@ PLUMMER_A = 3.0 * math.pi / 16.0
 GALAXY = (1.0, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0)
 # circular speed of that model at (8, 0, 0): sqrt(R |a_R|); pinned against the oracle's field
 V_CIRC_8 = 0.837866164494
+V_CIRC_10 = 0.821107211916  # circular speed of the same galaxy at R = 10
 ORBIT_R = 8.0
 
 DT_DEFAULT = 2.0 ** -11
@@ -128,6 +129,21 @@ def paper_timing(n: int, seed: int = 7000):
 
 
 PAPER_SIZES = [480 * 2 ** k for k in range(12)] + [1536000]  # 480 .. 983040, then 1,536,000
+BH_RATIOS = (0.1, 1.0, 50.0, 105.0)  # black-hole to cluster mass ratios of Table 8
+
+
+def paper_black_hole(ratio: float, n: int = 15360, seed: int = 8000):
+    """The collision set-up of Sect. 6.2 (Table 8): the uniform sphere with q = 0.3 and
+    eps = 0.005 / N^(1/3), centre of mass at (10, 0, 0) moving at (0, 0.001 v_c, 0), in the galaxy
+    with a point mass of `ratio` cluster masses at its centre (softened like a star); sym6 with
+    dt = 1e-4 (4e4 steps cover t = [0, 4])."""
+    p, v, m = uniform_sphere(n, seed + n)
+    p, v = on_orbit(p, v, R=10.0, vc=0.001 * V_CIRC_10)
+    eps = 0.005 / n ** (1.0 / 3.0)
+    b = single(p, v, m, eps, True, name="black-hole-%g-uniform-sphere-%d" % (ratio, n), integrator="sym6",
+               steps=40000, dt=1e-4)
+    b.galaxy = GALAXY + (float(ratio), eps)  # the cluster mass is 1
+    return b
 
 
 def uniform_box(n: int, seed: int, scale: float = 1.0, mass_range=(0.5, 1.5)):

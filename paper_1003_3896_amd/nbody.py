@@ -37,7 +37,7 @@ class NBodyError(RuntimeError):
 
 
 class nbody_galaxy(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("Mb", "ab", "Md", "ad", "bd", "vh", "dh")]
+    _fields_ = [(n, ctypes.c_double) for n in ("Mb", "ab", "Md", "ad", "bd", "vh", "dh", "Mbh", "ebh")]
 
 
 class nbody_system(ctypes.Structure):
@@ -141,7 +141,7 @@ class System:
         self.field = None if field is None else np.ascontiguousarray(
             np.broadcast_to(np.asarray(field, np.uint8), (B,)))
         self.G = float(G)
-        self.galaxy = tuple(float(v) for v in galaxy)
+        self.galaxy = tuple(float(v) for v in galaxy) + (0.0,) * (9 - len(galaxy))  # no black hole if 7
         self.prec = PREC[prec] if isinstance(prec, str) else int(prec)
         c = nbody_system()
         c.nclusters = B

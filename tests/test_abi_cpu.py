@@ -62,6 +62,8 @@ def test_workspace_bytes_and_interactions():
     dict(offsets=[0, 10], eps=[0.1], prec=7),            # unknown mode
     dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.0, 0.7, 12.0)),  # bd = 0
     dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, float("nan"))),
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0, -1.0, 0.0)),  # Mbh < 0
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0, 5.0, float("inf"))),
 ])
 def test_invalid_systems_rejected_on_host(bad):
     s = nbody.System(**bad)

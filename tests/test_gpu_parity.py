@@ -357,3 +357,28 @@ def test_local_mode_alone_equals_in_batch():
         s, e = b.offsets[c], b.offsets[c + 1]
         alone = inputs.single(b.pos[s:e], b.vel[s:e], b.mass[s:e], b.eps[c], bool(b.field[c]))
         assert np.array_equal(run(alone), a1[s:e]), c
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32dl"])
+def test_black_hole_field(prec):
+    """Sect. 6.2's central point mass in the field: a cluster passing close to it (the stiff case)
+    matches the oracle, internal and external terms together; in FP64 also along 10 sym6 steps."""
+    torch_dev()
+    b = inputs.paper_black_hole(50.0, n=2048)
+    b.pos = b.pos - np.array([9.95, 0.0, 0.0])  # barycentre 0.05 from the black hole
+    sim = make_sim(b, prec)
+    a = sim.accel().cpu().numpy()
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    print("\n[black hole %s] %s" % (prec, stats(err)), flush=True)
+    assert err.max() <= TOL[prec]
+    if prec == "fp64":
+        dt = 1e-4
+        a0 = oracle.total_accel(b.pos, b.mass, 1.0, b.eps[0], True, b.galaxy)
+        rp, rv, _ = oracle.step(b.pos, b.vel, b.mass, a0, dt, 10, "sym6", 1.0, b.eps[0], True, b.galaxy)
+        sim.step("sym6", dt, 10)
+        pos = sim.pos.cpu().numpy()
+        assert np.abs(pos - rp).max() <= 1e-10 * np.abs(rp).max()
+        e_gpu = sim.energy(prec="fp64")[0].cpu().numpy()
+        e_ref = oracle.energy(rp, rv, b.mass, 1.0, b.eps[0], True, b.galaxy)
+        assert abs(e_gpu[3] - e_ref[3]) <= 1e-11 * abs(e_ref[3])

@@ -41,3 +41,16 @@ def test_paper_timing_batch():
     assert inputs.PAPER_SIZES[0] == 480 and inputs.PAPER_SIZES[-1] == 1536000
     cm = (b.mass[:, None] * b.pos).sum(axis=0)
     assert abs(cm[0] - 8.0) < 1e-12 and abs(cm[1]) < 1e-12
+
+
+def test_black_hole_set_up():
+    """Table 8's start: barycentre at (10, 0, 0) with 0.001 of the local circular speed, the point
+    mass in cluster-mass units at the galaxy centre; V_CIRC_10 is the galaxy's circular speed."""
+    a, _ = oracle.ext_field(np.array([[10.0, 0.0, 0.0]]))
+    assert abs(math.sqrt(10 * abs(a[0, 0])) - inputs.V_CIRC_10) < 1e-12
+    b = inputs.paper_black_hole(50.0, n=960)
+    cm = (b.mass[:, None] * b.pos).sum(axis=0)
+    vcm = (b.mass[:, None] * b.vel).sum(axis=0)
+    assert abs(cm[0] - 10.0) < 1e-12 and abs(vcm[1] - 0.001 * inputs.V_CIRC_10) < 1e-15
+    assert b.galaxy[:7] == inputs.GALAXY and b.galaxy[7] == 50.0 and b.galaxy[8] == b.eps[0]
+    assert b.meta["integrator"] == "sym6" and b.meta["dt"] == 1e-4 and b.meta["steps"] == 40000

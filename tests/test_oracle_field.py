@@ -73,3 +73,54 @@ def test_torque_of_axisymmetric_field_has_no_z_component(oracle_mod):
     pos, vel = inputs.on_orbit(pos, vel)
     e = oracle_mod.energy(pos, vel, m, 1.0, 1e-3, field=True)
     assert abs(e[12]) < 1e-14 * abs(e[10:12]).max() + 1e-16
+
+
+BH_GALAXY = inputs.GALAXY + (50.0, 2e-3)
+
+
+def test_black_hole_is_minus_gradient_and_closed_form(oracle_mod):
+    """The central point mass (Sect. 6.2) alone against its softened Kepler potential, its
+    acceleration against the finite difference of the whole field with it, and G scaling."""
+    x = np.array([[1.5, -0.5, 0.7], [0.01, 0.002, -0.003]])
+    r2 = (x * x).sum(1)
+    a, phi = oracle_mod.ext_field(x, galaxy=(0.0, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0, 7.0, 0.05))
+    np.testing.assert_allclose(phi, -7.0 / np.sqrt(r2 + 0.0025), rtol=1e-15)
+    np.testing.assert_allclose(a, -7.0 * x / ((r2 + 0.0025) ** 1.5)[:, None], rtol=1e-14)
+    a2, _ = oracle_mod.ext_field(x, G=3.0, galaxy=(0.0, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0, 7.0, 0.05))
+    np.testing.assert_allclose(a2, 3 * a, rtol=1e-15)
+    # Mbh = 0 is the 7-parameter galaxy exactly
+    pts = np.array([[8.0, 0.1, 0.2], [0.3, -0.2, 0.1]])
+    np.testing.assert_array_equal(oracle_mod.ext_field(pts, galaxy=inputs.GALAXY + (0.0, 0.3))[0],
+                                  oracle_mod.ext_field(pts)[0])
+    rng = np.random.default_rng(8)
+    pts = np.concatenate([rng.uniform(-3, 3, (30, 3)), rng.uniform(-0.05, 0.05, (10, 3))])
+    a, _ = oracle_mod.ext_field(pts, galaxy=BH_GALAXY)
+    h = 1e-6
+    fd = np.zeros_like(pts)
+    for c in range(3):
+        dp = np.zeros(3)
+        dp[c] = h
+        fd[:, c] = -(oracle_mod.ext_field(pts + dp, galaxy=BH_GALAXY)[1]
+                     - oracle_mod.ext_field(pts - dp, galaxy=BH_GALAXY)[1]) / (2 * h)
+    err = np.linalg.norm(a - fd, axis=1) / np.linalg.norm(a, axis=1)
+    assert err.max() < 1e-7
+
+
+def test_kepler_orbit_around_the_black_hole(oracle_mod):
+    """A tracer around the point mass alone (no galaxy, no softening) on an e = 0.5 orbit follows
+    Kepler's equation after one sym6 integration over one and a half periods."""
+    M, a_k, e = 5.0, 1.0, 0.5
+    gal = (0.0, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0, M, 0.0)
+    r_p = a_k * (1 - e)
+    v_p = math.sqrt(M * (1 + e) / r_p)
+    pos = np.array([[r_p, 0.0, 0.0]])
+    vel = np.array([[0.0, v_p, 0.0]])
+    m = np.array([1e-9])
+    T = 2 * math.pi * math.sqrt(a_k ** 3 / M)
+    t = 1.5 * T
+    nsteps = 3000
+    acc = oracle_mod.total_accel(pos, m, 1.0, 0.0, field=True, galaxy=gal)
+    p, v, _ = oracle_mod.step(pos, vel, m, acc, t / nsteps, nsteps, "sym6", 1.0, 0.0, field=True, galaxy=gal)
+    # Kepler's equation: mean anomaly at t = 1.5 T is pi -> apocentre on the -x axis
+    assert abs(p[0, 0] + a_k * (1 + e)) < 1e-8 and abs(p[0, 1]) < 1e-7
+    assert abs(math.hypot(v[0, 0], v[0, 1]) - math.sqrt(M * (1 - e) / (a_k * (1 + e)))) < 1e-8

@@ -30,6 +30,8 @@ MUTANTS = [
     ("kinetic-half-missing", "nsum_add(&K, 0.5 * m * (v[0]", "nsum_add(&K, 1.0 * m * (v[0]"),
     ("L-index", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[0]));", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[1]));"),
     ("last-kick-missing", "kick(n, vel, acc, Kc[stages] * dt);", ";"),
+    ("bh-power", "G * Mbh / (q2 * sqrt(q2))", "G * Mbh / q2"),
+    ("bh-softening-dropped", "const double q2 = r2 + ebh * ebh;", "const double q2 = r2;"),
 ]
 
 
@@ -70,6 +72,13 @@ def _pins():
         fd[:, c] = -(oracle.ext_field(pts + dp)[1] - oracle.ext_field(pts - dp)[1]) / (2 * h)
     if (np.linalg.norm(a - fd, axis=1) / np.linalg.norm(a, axis=1)).max() > 1e-8:
         fails.append("field-fd")
+    # the central point mass: closed form and finite differences
+    gal = (0.0, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0, 7.0, 0.05)
+    xb = rng.uniform(-0.3, 0.3, (6, 3))
+    ab, pb = oracle.ext_field(xb, galaxy=gal)
+    q2 = (xb * xb).sum(1) + 0.0025
+    if np.abs(pb + 7.0 / np.sqrt(q2)).max() > 1e-13 or np.abs(ab + 7.0 * xb / (q2 ** 1.5)[:, None]).max() > 1e-11:
+        fails.append("bh-closed-form")
     a8, _ = oracle.ext_field(np.array([[8.0, 0, 0]]))
     if abs(math.sqrt(8 * abs(a8[0, 0])) - inputs.V_CIRC_8) > 1e-12:
         fails.append("field-vc")
