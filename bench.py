@@ -333,7 +333,14 @@ def bench_c5(args):
     rate = args.load * xsat / mean_work
     jobs = inputs.c5_jobs(args.jobs, rate)
     reqs = serve_requests(jobs)
-    srv = Server(ex, energy=True, policy=args.policy, fill=args.fill)
+    count = [0]
+
+    def progress(r):
+        count[0] += 1
+        if count[0] % 20 == 0:
+            print("c5: %d / %d jobs done" % (count[0], len(reqs)), file=sys.stderr, flush=True)
+
+    srv = Server(ex, energy=True, policy=args.policy, fill=args.fill, on_result=progress)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     el = time.perf_counter() - t0

@@ -226,7 +226,7 @@ class Server:
 
     def __init__(self, executor, energy: bool = True, clock=time.perf_counter, sym6=None, round_budget_s: float = 4e-3,
                  rate_estimate: float = 2e12, max_rounds_per_call: int = 64, policy: str = "srpt",
-                 fill: float = 2.0 ** 30):
+                 fill: float = 2.0 ** 30, on_result=None):
         if policy not in ("srpt", "all"):
             raise ValueError("policy must be 'srpt' or 'all'")
         self.ex = executor
@@ -236,6 +236,7 @@ class Server:
         # short jobs are not held to the round rate of the largest ones.
         self.policy = policy
         self.fill = float(fill)
+        self.on_result = on_result  # called with every Result as it is recorded (progress, logging)
         self.energy = energy
         self.clock = clock
         # rounds are chained in one call while no job starts or ends, up to about round_budget_s of
@@ -368,6 +369,8 @@ class Server:
             bad = (not np.all(np.isfinite(pos))) or (not np.all(np.isfinite(vel))) or (e1 is not None and e1[15] != 0)
             self.results[a.req.jid] = Result(a.req.jid, "failed" if bad else "done", now_fn() - a.req.arrival, pos,
                                              vel, a.energy0, e1, "non-finite state" if bad else "")
+            if self.on_result:
+                self.on_result(self.results[a.req.jid])
         # compaction: keep survivors in admission order, contiguous from 0
         keep = [a for a in self.active if a not in done]
         off = 0
