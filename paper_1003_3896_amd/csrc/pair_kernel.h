@@ -1,8 +1,9 @@
 // All-pairs softened gravity (Sect. 2, Eq. 5) for gfx950: kernel templates.
 //
 // Persistent ragged kernel.  The grid holds a few blocks per CU; each block repeatedly takes the
-// next work item (one i-tile of one cluster) from a device counter.  Items are ordered largest
-// cluster first, so long items start early and short ones fill the tail.
+// next work item (one i-tile of one cluster against one j-range of it) from a device counter.
+// Items are ordered longest j-range first, so long items start early and short ones fill the
+// tail, and j-range major within a cluster, so the blocks running together share sources in L2.
 //
 // Block = 4 wavefronts of 64 lanes.  The 4 waves form 4/W groups; the W waves of a group hold
 // the same K*64 i-particles (K per lane, in registers) and split every j-tile between them, so a
@@ -22,7 +23,7 @@
 // that centre is computed in plain FP32 on the local coordinates: rounding both
 // coordinates to FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction
 // by 2^-24 |d| more, at most 2^-22 |d| in all (R = D/2 <= |d|), so such a term is as accurate as
-// a double-single one up to a small factor; other shares run the double-single loop.
+// a double-single one up to a small factor; other tiles run the double-single loop.
 //
 // The results for a particle depend only on its own cluster's data and on (T, W) (in the local
 // family also on K, which sets the i-tile each coordinate frame is centred on): never on the other
