@@ -38,9 +38,11 @@ def test_workspace_bytes_and_interactions():
     ws = nbody.nbody_workspace_bytes(None, s)
     assert ws >= 8 * b.n and ws % 256 == 0
     assert nbody.nbody_interactions(s) == b.interactions_per_eval()
-    # workspace does not depend on precision beyond the record area bound
+    # workspace does not depend on precision, except for the local mode's sort buffers
     for p in ("fp32", "fp32c", "fp64"):
         assert nbody.nbody_workspace_bytes(None, s.with_prec(p)) == ws
+    wdl = nbody.nbody_workspace_bytes(None, s.with_prec("fp32dl"))
+    assert wdl >= ws + 48 * b.n and wdl <= nbody.nbody_workspace_bytes_max(b.n, b.B)
     # the batch-independent bound covers it, and covers adversarial batches of the same totals
     bound = nbody.nbody_workspace_bytes_max(b.n, b.B)
     assert bound >= ws
@@ -106,6 +108,7 @@ def test_workspace_bound_holds_for_random_batches():
         B = int(rng.integers(1, 40))
         sizes = np.exp(rng.uniform(0, np.log(70000), B)).astype(np.int64) + 1
         offs = np.concatenate([[0], np.cumsum(sizes)])
-        ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3))
+        prec = ("fp32ds", "fp32dl", "fp64")[int(rng.integers(0, 3))]
+        ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3, prec=prec))
         cap = int(offs[-1]) + int(rng.integers(0, 1000))
         assert ws <= nbody.nbody_workspace_bytes_max(cap, B + int(rng.integers(0, 5)))
