@@ -34,7 +34,7 @@
  *              precision-recovery scheme of Sect. 5.2.
  *   NB_FP64    all FP64.
  *   NB_FP32DL  the accuracy of NB_FP32DS at close to the cost of NB_FP32C: each evaluation sorts
- *              every cluster's particles along a Morton curve of their FP64 positions; each pair
+ *              every cluster's particles along a Hilbert curve of their FP64 positions; each pair
  *              work item takes coordinates relative to the centre of its own i-particles' bounding
  *              box; a j-tile all of whose sources lie at least one box diagonal from that centre
  *              is computed in FP32 on those local coordinates (coordinate-difference error at

@@ -1,8 +1,8 @@
-// Morton-order sort of every cluster's particles for the NB_FP32DL mode (gfx950).
+// Space-filling-curve sort of every cluster's particles for the NB_FP32DL mode (gfx950).
 //
 // The pair kernel of that mode centres each work item's coordinates on its own i-particles, which
 // pays off only when the particles of an i-tile (and of a j-tile) lie close together; sorting
-// along a Morton curve of the positions makes consecutive particles spatial neighbours.  The sort
+// along a Hilbert curve of the positions makes consecutive particles spatial neighbours.  The sort
 // is a stable least-significant-digit radix sort of 30-bit keys (10 bits per axis, relative to the
 // cluster's bounding box) in three passes of 10 bits.  Sort tiles never span clusters, so every
 // cluster is sorted on its own, and the result depends only on that cluster's positions: ties
@@ -23,12 +23,43 @@ __device__ __forceinline__ unsigned spread3(unsigned v) {
   return v;
 }
 
+// Index of the cell (x, y, z) (10 bits each) along a 3-D Hilbert curve, whose consecutive cells
+// are always face neighbours (a Morton order jumps), so runs of consecutive particles have small
+// bounding boxes.  Skilling's transpose method (Programming the Hilbert curve, AIP Conf. Proc.
+// 707, 2004): undo the excess work of the inverse Gray code level by level, Gray-encode, then
+// interleave the bits (bit b of axis a goes to key bit 3b + 2 - a).
+__device__ __forceinline__ unsigned hilbert3(unsigned x, unsigned y, unsigned z) {
+  unsigned X[3] = {x, y, z};
+  for (unsigned Q = 1u << (kRadixBits - 1); Q > 1; Q >>= 1) {
+    const unsigned P = Q - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;  // invert the low bits
+      } else {      // exchange the low bits of X[0] and X[i]
+        const unsigned t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  unsigned t = 0;
+  for (unsigned Q = 1u << (kRadixBits - 1); Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) X[i] ^= t;
+  return (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
+}
+
 __device__ __forceinline__ unsigned cell(double x, double lo, double scale) {
   const double q = (x - lo) * scale;
   return q <= 0.0 ? 0u : q >= (double)(kRadix - 1) ? (unsigned)(kRadix - 1) : (unsigned)q;
 }
 
-// Keys of one O(N) chunk: Morton code of the position in the cluster's box, value = local index.
+// Keys of one O(N) chunk: Hilbert index of the position's cell in the cluster's box (1024 cells
+// per axis), value = local index.
 __global__ __launch_bounds__(kBlock) void k_keys(Args a) {
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
@@ -37,14 +68,14 @@ __global__ __launch_bounds__(kBlock) void k_keys(Args a) {
   const int l = ch.start + t;
   const long long g = c.off + l;
   const double* b = a.box + 6 * (size_t)ch.cluster;
-  unsigned code = 0;
+  unsigned q[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double ext = b[3 + d] - b[d];
     const double scale = ext > 0.0 ? (double)kRadix / ext : 0.0;
-    code |= spread3(cell(a.pos[3 * g + d], b[d], scale)) << d;
+    q[d] = cell(a.pos[3 * g + d], b[d], scale);
   }
-  a.skey[0][g] = code;
+  a.skey[0][g] = hilbert3(q[0], q[1], q[2]);
   a.sval[0][g] = l;
 }
 

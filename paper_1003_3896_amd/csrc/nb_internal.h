@@ -10,11 +10,11 @@ constexpr int kBlock = 256;
 constexpr int kChunk = 256;
 
 // Precision families of the pair kernel (FAM_DL: double-single near j-tiles, FP32 on coordinates
-// centred on the i-tile for far ones, particles in Morton order).
+// centred on the i-tile for far ones, particles in Hilbert-curve order).
 enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2, FAM_DL = 3 };
 constexpr int kFamilies = 4;
 
-// Morton sort of the NB_FP32DL mode: particles per sort tile (one block), radix digit bits.
+// Hilbert-curve sort of the NB_FP32DL mode: particles per sort tile (one block), radix digit bits.
 constexpr int kSortTile = 2048;
 constexpr int kRadixBits = 10;
 constexpr int kRadix = 1 << kRadixBits;
@@ -64,7 +64,7 @@ struct Args {
   double* partials;    // [nchunks][11] chunk sums m x, m y, m z, m, count of masses != the cluster's
                        // first; then min x, y, z and max x, y, z
   double* box;         // [B][6] bounding box of each cluster (min xyz, max xyz)
-  // Morton sort (NB_FP32DL): keys and local indices (double-buffered), per-tile digit counts and
+  // Hilbert-curve sort (NB_FP32DL): keys and local indices (double-buffered), per-tile digit counts and
   // offsets, and the result: perm[off + l] = local index of the particle at sorted position l
   const Chunk* stiles;
   int nstiles;
@@ -107,7 +107,7 @@ hipError_t launch_pair(const Args& a, const TileCfg& t, int grid, bool mask, boo
                        hipStream_t s);
 hipError_t launch_energy(const Args& a, hipStream_t s);
 hipError_t launch_combine(const Args& a, bool potmode, bool kick, hipStream_t s);
-// Morton sort: leaves the permutation in sval[1] and the sorted (x, y, z, m) in spos
+// Hilbert-curve sort: leaves the permutation in sval[1] and the sorted (x, y, z, m) in spos
 hipError_t launch_sort(const Args& a, int B, hipStream_t s);
 
 

@@ -18,7 +18,7 @@
 // it into FP64 after every tile; pure-FP32 mode keeps one FP32 sum.  The double-single family forms
 // each coordinate difference as (xj_hi - xi_hi) + (xj_lo - xi_lo): the hi difference is exact for
 // close pairs, so the difference carries FP32 relative accuracy however close the pair is.
-// The local family (particles in Morton order) centres every coordinate on the bounding box of
+// The local family (particles in Hilbert-curve order) centres every coordinate on the bounding box of
 // the work item's i-particles; a full j-tile that lies entirely at least one box diagonal D from
 // that centre is computed in plain FP32 on the local coordinates: rounding both
 // coordinates to FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction

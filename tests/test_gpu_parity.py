@@ -314,7 +314,7 @@ def test_equal_and_nearly_equal_masses(prec):
 
 @pytest.mark.parametrize("tile", [(2, 4, 256, 4, 0), (2, 2, 256, 8, 0), (1, 4, 128, 8, 0), (2, 4, 128, 4, 0)])
 def test_local_mode_shapes_and_order(tile):
-    """The Morton-sorted local mode returns every particle's result at its own index and meets the
+    """The Hilbert-sorted local mode returns every particle's result at its own index and meets the
     double-single bound in every compiled shape on a cluster large enough to have far tiles;
     repeated evaluations are bitwise identical."""
     torch_dev()
