@@ -185,7 +185,7 @@ const char* nbody_last_error(void);
 
 /* Pair-kernel launch shape for one precision family and cluster-size class:
  *   prec  NB_FP32 / NB_FP32C (share a kernel), NB_FP32DS, NB_FP64 or NB_FP32DL
- *   nclass 0: largest cluster < 2048 particles, 1: < 32768, 2: larger
+ *   nclass 0: largest cluster < 2048 particles, 1: < 32768, 2: < 131072, 3: larger
  *   k     i-particles per lane; waves_per_group  wavefronts sharing the same i-particles, each
  *         taking 1/waves_per_group of every j-tile; (k, waves_per_group) in {(1,1), (1,2), (1,4),
  *         (2,2), (2,4)}; one work item covers 256 k / waves_per_group particles

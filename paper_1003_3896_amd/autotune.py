@@ -22,7 +22,7 @@ SHAPES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4)]
 # (k, w, tile) shapes that also have the rsq-phased loop (FP32 families)
 PHASED = {(1, 4, 256), (2, 2, 256), (2, 4, 128), (2, 4, 256)}
 TILES = [128, 256]
-BLOCKS_PER_CU = [2, 4, 8]
+BLOCKS_PER_CU = [2, 4, 6, 8]
 FAMILY = {"fp32": "f32", "fp32c": "f32", "fp32ds": "ds", "fp64": "f64", "fp32dl": "dl"}
 # shapes the local double-single family does not compile
 NOT_DL = {(1, 1), (1, 2)}
@@ -33,7 +33,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.js
 
 
 def size_class(maxn: int) -> int:
-    return 0 if maxn < 2048 else 1 if maxn < 32768 else 2
+    return 0 if maxn < 2048 else 1 if maxn < 32768 else 2 if maxn < 131072 else 3
 
 
 def _scale(a_all: np.ndarray, rows) -> np.ndarray:
@@ -135,16 +135,19 @@ def apply(ctx, arch: str = "gfx950", path: str = CACHE, fixed_tile: Optional[Dic
 
 
 def representative(nclass: int):
-    """A workload of each size class: small ragged ensemble, the C4-like ensemble, one big cluster."""
+    """A workload of each size class: small ragged ensemble, the C4-like ensemble, the C2 cluster
+    (65536 Salpeter stars), the C3 cluster (262144)."""
     from . import inputs
     if nclass == 0:
         return inputs.c4(B=256, lo=256, hi=2047)
     if nclass == 1:
         return inputs.c4()
+    if nclass == 2:
+        return inputs.c2()
     return inputs.c3()
 
 
-def tune_all(precs=("fp32c", "fp32ds", "fp64", "fp32dl"), classes=(0, 1, 2), path: str = CACHE, verbose: bool = True) -> Dict:
+def tune_all(precs=("fp32c", "fp32ds", "fp64", "fp32dl"), classes=(0, 1, 2, 3), path: str = CACHE, verbose: bool = True) -> Dict:
     """Sweep every (precision family, size class) on its representative workload and cache the
     fastest shape that passes the accuracy gate."""
     out = {}

@@ -13,6 +13,8 @@ constexpr int kChunk = 256;
 // centred on the i-tile for far ones, particles in Hilbert-curve order).
 enum Family { FAM_F32 = 0, FAM_DS = 1, FAM_F64 = 2, FAM_DL = 3 };
 constexpr int kFamilies = 4;
+// Cluster-size classes of the launch-shape table (largest cluster < 2048, < 32768, < 131072, larger).
+constexpr int kSizeClasses = 4;
 
 // Hilbert-curve sort of the NB_FP32DL mode: particles per sort tile (one block), radix digit bits.
 constexpr int kSortTile = 2048;

@@ -102,7 +102,7 @@ int split_of(int n) {
   return s;
 }
 
-int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : 2; }
+int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : maxn < 131072 ? 2 : 3; }
 int family_of(int prec) {
   return prec == NB_FP64 ? FAM_F64 : prec == NB_FP32DS ? FAM_DS : prec == NB_FP32DL ? FAM_DL : FAM_F32;
 }
@@ -124,7 +124,7 @@ struct nbody_ctx {
   hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<StepGraph> gcache;  // small LRU cache of captured graphs (most recent last)
-  TileCfg tiles[kFamilies][3];
+  TileCfg tiles[kFamilies][kSizeClasses];
   Slot slots[4];
   int next_slot = 0;
   bool timing = false;
@@ -493,7 +493,7 @@ int check_state(const Plan& p, const void* pos, const void* vel, const void* mas
 
 void default_tiles(nbody_ctx* ctx) {
   for (int f = 0; f < kFamilies; ++f)
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < kSizeClasses; ++c)
       ctx->tiles[f][c] = c == 0 ? TileCfg{1, 4, 128, 8, 0}
                        : f == FAM_F32 ? TileCfg{2, 4, 256, 4, 0}
                                       : TileCfg{2, 4, 256, 8, 0};
@@ -834,7 +834,7 @@ int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, con
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile) {
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
   if (prec < NB_FP32 || prec > NB_FP32DL) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
-  if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
+  if (nclass < 0 || nclass >= kSizeClasses) return fail(NB_ERR_ARG, "size class must be 0, 1, 2 or 3");
   TileCfg t{tile.k, tile.waves_per_group, tile.tile, tile.blocks_per_cu, tile.phased};
   const int fam = family_of(prec);
   if (!tile_supported(fam, t))
@@ -847,7 +847,7 @@ int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile) {
   if (!ctx || !tile) return fail(NB_ERR_ARG, "NULL argument");
   if (prec < NB_FP32 || prec > NB_FP32DL) return fail(NB_ERR_ARG, "unknown precision mode %d", prec);
-  if (nclass < 0 || nclass > 2) return fail(NB_ERR_ARG, "size class must be 0, 1 or 2");
+  if (nclass < 0 || nclass >= kSizeClasses) return fail(NB_ERR_ARG, "size class must be 0, 1, 2 or 3");
   const TileCfg& t = ctx->tiles[family_of(prec)][nclass];
   tile->k = t.k;
   tile->waves_per_group = t.w;

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 NB_OK, NB_ERR_ARG, NB_ERR_HIP, NB_ERR_NOMEM, NB_ERR_UNSUPPORTED, NB_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 NB_FP32, NB_FP32C, NB_FP32DS, NB_FP64, NB_FP32DL = 0, 1, 2, 3, 4
 PREC = {"fp32": NB_FP32, "fp32c": NB_FP32C, "fp32ds": NB_FP32DS, "fp64": NB_FP64, "fp32dl": NB_FP32DL}
+# cluster-size classes of the launch-shape table (nbody_set_tile)
+N_CLASSES = 4
 
 EXPORTS = (
     "nbody_create", "nbody_destroy", "nbody_workspace_bytes", "nbody_accel", "nbody_substep",

@@ -135,7 +135,7 @@ class HipExecutor:
             autotune.apply(self.ctx, fixed_tile={fam: SERVE_TILE for fam in ("f32", "ds", "f64", "dl")})
         else:
             for p in {prec, energy_prec}:
-                for ncl in range(3):
+                for ncl in range(nbody.N_CLASSES):
                     nbody.nbody_set_tile(self.ctx, p, ncl, *tile)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.pos = torch.zeros(self.capacity, 3, **f64)

@@ -269,7 +269,7 @@ def test_launch_shapes_agree(prec, tile):
     p, v, m = inputs.plummer(3000, 4321)
     b = inputs.single(p, v, m, 1e-3)
     sim = make_sim(b, prec)
-    for ncl in range(3):
+    for ncl in range(nbody.N_CLASSES):
         nbody.nbody_set_tile(sim.ctx, prec, ncl, *tile)
     a = sim.accel().cpu().numpy().copy()
     ref, scale = oracle_reference(b)
@@ -278,7 +278,7 @@ def test_launch_shapes_agree(prec, tile):
         assert err.max() <= TOL[prec]
     assert np.median(err) <= TOL_MEDIAN[prec]
     if tile[4] == 1:  # the phased loop does the same arithmetic per term as the plain one
-        for ncl in range(3):
+        for ncl in range(nbody.N_CLASSES):
             nbody.nbody_set_tile(sim.ctx, prec, ncl, *tile[:4], 0)
         assert np.array_equal(sim.accel().cpu().numpy(), a)
 
@@ -322,7 +322,7 @@ def test_local_mode_shapes_and_order(tile):
     p, v, m = inputs.plummer(20000, 4711)
     b = inputs.single(p, v, m, 1e-3)
     sim = make_sim(b, "fp32dl")
-    for ncl in range(3):
+    for ncl in range(nbody.N_CLASSES):
         nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile)
     a = sim.accel().cpu().numpy().copy()
     assert np.array_equal(sim.accel().cpu().numpy(), a)
@@ -332,7 +332,7 @@ def test_local_mode_shapes_and_order(tile):
     assert err.max() <= TOL["fp32dl"]
     assert np.median(err) <= TOL_MEDIAN["fp32dl"]
     # blocks per CU (the grid) change nothing
-    for ncl in range(3):
+    for ncl in range(nbody.N_CLASSES):
         nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile[:3], 2, 0)
     assert np.array_equal(sim.accel().cpu().numpy(), a)
 
@@ -346,7 +346,7 @@ def test_local_mode_alone_equals_in_batch():
 
     def run(batch):
         sim = make_sim(batch, "fp32dl")
-        for ncl in range(3):
+        for ncl in range(nbody.N_CLASSES):
             nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, 2, 4, 256, 4, 0)
         return sim.accel().cpu().numpy().copy()
 
