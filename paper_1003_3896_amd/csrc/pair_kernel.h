@@ -62,6 +62,42 @@ __device__ __forceinline__ int next_item(const Args& a, int* s_item) {
   return it < a.nitems ? it : -1;
 }
 
+// Work-item data is the same in every lane; passing it through readfirstlane lets the compiler
+// keep it in scalar registers, which leaves the vector registers to the pair loop.
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long wave_uniform(long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(x & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_uniform(double x) {
+  return __longlong_as_double(wave_uniform(__double_as_longlong(x)));
+}
+__device__ __forceinline__ float wave_uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ PairItem load_item(const Args& a, int it) {
+  const PairItem p = a.items[it];
+  return PairItem{wave_uniform(p.cluster), wave_uniform(p.i0), wave_uniform(p.js), 0};
+}
+__device__ __forceinline__ DevCluster load_cluster(const Args& a, int b) {
+  const DevCluster c = a.cl[b];
+  DevCluster u;
+  u.off = wave_uniform(c.off);
+  u.part_off = wave_uniform(c.part_off);
+  u.n = wave_uniform(c.n);
+  u.flags = wave_uniform(c.flags);
+  u.eps2 = wave_uniform(c.eps2);
+  u.eps2f = wave_uniform(c.eps2f);
+  u.chunk0 = wave_uniform(c.chunk0);
+  u.nchunks = wave_uniform(c.nchunks);
+  u.split = wave_uniform(c.split);
+  u.jlen = wave_uniform(c.jlen);
+  u.stile0 = wave_uniform(c.stile0);
+  u.nstiles = wave_uniform(c.nstiles);
+  return u;
+}
+
 // One thread's share of a j-tile, fetched from the FP64 state into registers ahead of its use so
 // that the global-memory latency overlaps the previous tile's arithmetic.
 struct TileRaw {
@@ -297,10 +333,14 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / W, sub = wave % W;
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
-    const PairItem item = a.items[it];
-    const DevCluster c = a.cl[item.cluster];
+    // (the local family keeps the work-item data in vector registers: its 80-VGPR build ran slower
+    // with the extra scalar-register pressure)
+    const PairItem item = LOC ? a.items[it] : load_item(a, it);
+    const DevCluster c = LOC ? a.cl[item.cluster] : load_cluster(a, item.cluster);
     double4 ref = a.ref[item.cluster];
-    const double mc = a.mconst[item.cluster];  // != 0: every mass of the cluster equals mc
+    if constexpr (!LOC) ref = make_double4(wave_uniform(ref.x), wave_uniform(ref.y), wave_uniform(ref.z), 0.0);
+    // != 0: every mass of the cluster equals mc
+    const double mc = LOC ? a.mconst[item.cluster] : wave_uniform(a.mconst[item.cluster]);
     const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
     float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K];
