@@ -499,8 +499,10 @@ __global__ __launch_bounds__(kBlock) void k_pair32(Args a, int kick) {
   pair32_items<FAM, K, W, T, FOLD, MASK, POT, PH>(a, kick);
 }
 
-// The local family keeps 4 waves per SIMD (at most 128 VGPRs): with both loops in one kernel the
-// compiler would otherwise settle on 3, and the extra wave hides more of the FP32 chain's latency.
+// The local family is built for 6 waves per SIMD (at most 80 VGPRs): with both loops in one kernel
+// the compiler would otherwise settle on 3, and the extra waves hide more of the FP32 chain's
+// latency.  The price is a few dozen work-item set-up values spilled to scratch and reloaded once
+// per tile, outside the pair loops.
 template <int K, int W, int T, bool MASK, bool POT>
 __global__ __launch_bounds__(kBlock, 6) void k_pair32_local(Args a, int kick) {
   pair32_items<FAM_DL, K, W, T, true, MASK, POT, false>(a, kick);
