@@ -286,7 +286,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
   return NB_OK;
 }
 
-// Pair work items for i-tiles of kBlock*K particles, largest clusters first (ties by index).
+// Pair work items for i-tiles of 64 K (4 / W) particles (item_tile), longest j-ranges first (ties
+// by cluster index).
 void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   std::vector<int> order(p.B);
   for (int b = 0; b < p.B; ++b) order[b] = b;
