@@ -36,9 +36,9 @@
  *   NB_FP32DL  the accuracy of NB_FP32DS at close to the cost of NB_FP32C: each evaluation sorts
  *              every cluster's particles along a Hilbert curve of their FP64 positions; each pair
  *              work item takes coordinates relative to the centre of its own i-particles' bounding
- *              box; a j-tile all of whose sources lie at least one box diagonal from that centre
- *              is computed in FP32 on those local coordinates (coordinate-difference error at
- *              most 2^-22 relative), any other in double-single as NB_FP32DS.  Sums folded into
+ *              box; a j-tile all of whose sources lie at least 3/4 of the box diagonal from that
+ *              centre is computed in FP32 on those local coordinates (coordinate-difference error
+ *              at most 1.5 x 2^-22 relative), any other in double-single as NB_FP32DS.  Sums folded into
  *              FP64 per tile as in NB_FP32C.
  *
  * Errors

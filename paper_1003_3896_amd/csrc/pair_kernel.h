@@ -19,11 +19,12 @@
 // each coordinate difference as (xj_hi - xi_hi) + (xj_lo - xi_lo): the hi difference is exact for
 // close pairs, so the difference carries FP32 relative accuracy however close the pair is.
 // The local family (particles in Hilbert-curve order) centres every coordinate on the bounding box of
-// the work item's i-particles; a full j-tile that lies entirely at least one box diagonal D from
-// that centre is computed in plain FP32 on the local coordinates: rounding both
-// coordinates to FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction
-// by 2^-24 |d| more, at most 2^-22 |d| in all (R = D/2 <= |d|), so such a term is as accurate as
-// a double-single one up to a small factor; other tiles run the double-single loop.
+// the work item's i-particles; a full j-tile that lies entirely at least 3/4 of the box diagonal D
+// from that centre is computed in plain FP32 on the local coordinates: rounding both coordinates to
+// FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction by 2^-24 |d|
+// more, at most 1.5 x 2^-22 |d| in all (R = D/2 <= 2 |d|, since |d| >= 3/4 D - R), so such a term
+// is as accurate as a double-single one up to a small factor; other tiles run the double-single
+// loop.
 //
 // The results for a particle depend only on its own cluster's data and on (T, W) (in the local
 // family also on K, which sets the i-tile each coordinate frame is centred on): never on the other
@@ -355,7 +356,7 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     }
     double far2 = INFINITY;  // LOC: a j-record at |x_j - ref|^2 >= far2 is far from every i-particle
     if constexpr (LOC) {
-      // bounding box of the item's i-particles (FP64); ref = its centre, far2 = its diagonal^2
+      // bounding box of the item's i-particles (FP64); ref = its centre, far2 = (3/4 diagonal)^2
       double v[6];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -386,7 +387,7 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
       }
       ref = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]), 0.0);
       const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
-      far2 = (dx * dx + dy * dy + dz * dz) * (1.0 + 1e-6);
+      far2 = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -415,7 +416,7 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
       bool far = false;
       if constexpr (LOC) {
         // a full tile is far when every record of it is (then the FP32 difference of the local
-        // coordinates is within 2^-22 relative of the exact one); decided for the whole block, so
+        // coordinates is within 1.5 x 2^-22 relative of the exact one); decided for the whole block, so
         // its waves take the same path and meet at the tile barriers together
         bool ok = cnt == T;
         if (ok && threadIdx.x < T) {

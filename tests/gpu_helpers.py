@@ -11,7 +11,7 @@ import oracle
 #   ~8 FP32 roundings (2^-24 each) per term, tile sums folded into FP64 -> 1e-6
 #   FP32C: as FP32DS plus the rounding of the centred coordinates themselves, which perturbs a
 #   pair term by ~2^-24 |x| / |d| (unbounded for close pairs) -> gated on the median only
-#   FP32DL: far j-tiles have coordinate differences within 2^-22 relative (local centring), near
+#   FP32DL: far j-tiles have coordinate differences within 1.5 x 2^-22 relative (local centring), near
 #   ones are double-single -> 1e-6 as FP32DS
 TOL = {"fp64": 1e-12, "fp32ds": 1e-6, "fp32dl": 1e-6}
 TOL_MEDIAN = {"fp64": 1e-14, "fp32ds": 1e-7, "fp32c": 1e-6, "fp32dl": 1e-7}
