@@ -2,6 +2,7 @@
 finite differences of its potential, circular-speed closed form, Sect. 6.1's orbital period of
 about 60 time units at R = 8, and exact L_z conservation for the axisymmetric field (Table 2)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -44,12 +45,27 @@ def test_component_closed_forms(oracle_mod):
     np.testing.assert_allclose(a2, 2 * a1, rtol=1e-15)
 
 
+def _golden(name):
+    """key value pairs of a fixture under tests/golden/ (comment lines start with #)"""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    out = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
 def test_circular_speed_and_period(oracle_mod):
+    """The circular orbit at R = 8 in the oracle's galaxy has the period Sect. 6.1 prints."""
+    g = _golden("sect6_orbital_period.txt")
+    assert g["radius"] == inputs.ORBIT_R
     a, _ = oracle_mod.ext_field(np.array([[inputs.ORBIT_R, 0.0, 0.0]]))
     vc = math.sqrt(inputs.ORBIT_R * abs(a[0, 0]))
     assert abs(vc - inputs.V_CIRC_8) < 1e-12
     period = 2 * math.pi * inputs.ORBIT_R / vc
-    assert 59.0 < period < 61.0
+    assert abs(period - g["period"]) < g["tolerance"]
     assert a[0, 1] == 0 and a[0, 2] == 0
 
 
