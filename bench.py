@@ -584,7 +584,7 @@ def main():
 
     modes = {}
     if not args.no_modes and args.workload in ("c2", "c3", "c4"):
-        others = {"c3": ("fp32ds", "fp32c", "fp32", "fp64"), "c2": ("fp32ds", "fp64"), "c4": ("fp32dl",)}
+        others = {"c3": ("fp32ds", "fp32c", "fp32", "fp64"), "c2": ("fp32ds", "fp32c", "fp64"), "c4": ("fp32dl",)}
         for m in others[args.workload]:
             if m == prec:
                 continue
