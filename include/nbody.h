@@ -15,7 +15,9 @@
  *   owns particles [offsets[b], offsets[b+1]) of every particle array.  All particle arrays are
  *   DEVICE pointers to contiguous row-major float64 data: pos, vel, acc are (Ntot, 3), mass and
  *   pot are (Ntot).  The caller owns them, the workspace and the context; the library never
- *   allocates device memory on a call path and never synchronises the stream.
+ *   allocates device memory on a call path and never synchronises the stream (a call may wait on
+ *   the host for the table upload of the fourth-previous call to finish, to reuse its pinned
+ *   staging buffer).
  *
  * Units and signs
  *   a_i = G sum_{j != i} m_j d_ij / (|d_ij|^2 + eps_b^2)^{3/2} + a_ext(x_i),  d_ij = x_j - x_i
@@ -38,8 +40,8 @@
  *              work item takes coordinates relative to the centre of its own i-particles' bounding
  *              box; a j-tile all of whose sources lie at least 3/4 of the box diagonal from that
  *              centre is computed in FP32 on those local coordinates (coordinate-difference error
- *              at most 1.5 x 2^-22 relative), any other in double-single as NB_FP32DS.  Sums folded into
- *              FP64 per tile as in NB_FP32C.
+ *              at most 1.5 x 2^-22 relative), any other in double-single as NB_FP32DS.  Sums
+ *              folded into FP64 per tile as in NB_FP32C.
  *
  * Errors
  *   Every function returns NB_OK (0) or a negative status.  All argument checks run on the host
@@ -189,9 +191,11 @@ const char* nbody_last_error(void);
  *   k     i-particles per lane; waves_per_group  wavefronts sharing the same i-particles, each
  *         taking 1/waves_per_group of every j-tile; (k, waves_per_group) in {(1,1), (1,2), (1,4),
  *         (2,2), (2,4)}; one work item covers 256 k / waves_per_group particles
+ *         (NB_FP32DL: (1,4), (2,2), (2,4) only)
  *   tile  j-records per LDS tile (128 or 256); FP32 partial sums are folded into FP64 after every
  *         tile/waves_per_group terms, so tile and waves_per_group change the last bits of FP32-mode
- *         results while k and blocks_per_cu never do
+ *         results while k and blocks_per_cu never do (in NB_FP32DL k does too: it sets the work
+ *         item whose bounding box the local coordinates are centred on)
  *   blocks_per_cu  persistent blocks per compute unit (1..8)
  *   phased  FP32 families only: full tiles are evaluated in groups of 8 pair terms whose
  *         reciprocal square roots issue back to back (shapes (1,4,256), (2,2,256), (2,4,*));
