@@ -21,7 +21,8 @@ def _reqs(prec_tag, count=10):
 
 
 @pytest.mark.parametrize("prec,policy,fill", [("fp32ds", "srpt", 2.0 ** 30), ("fp32ds", "srpt", 4e6),
-                                              ("fp32ds", "all", 0.0), ("fp64", "srpt", 2.0 ** 30)])
+                                              ("fp32ds", "all", 0.0), ("fp64", "srpt", 2.0 ** 30),
+                                              ("fp32dl", "srpt", 2.0 ** 30)])
 def test_alone_equals_in_mix(prec, policy, fill):
     """20 jobs (sizes 128..3000 across two size classes, both integrators, field on some) served
     together, with queueing, reordering and partial rounds, give bitwise their results alone."""
