@@ -76,7 +76,7 @@ def workload(name):
 ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
 
 
-PROFILE_TAG = {"c3": "plummer262144"}  # workloads with a committed counter summary
+PROFILE_TAG = {"c3": "plummer262144", "c2": "salpeter65536"}  # workloads with a committed counter summary
 # sources that decide what a pair-kernel launch does (its code, work items and split rule)
 PAIR_SOURCES = [os.path.join(ROOT, "paper_1003_3896_amd", "csrc", f)
                 for f in ("pair_kernel.h", "nb_device.h", "nb_internal.h", "runtime.hip")]
