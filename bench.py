@@ -321,7 +321,7 @@ def bench_c5(args):
     from paper_1003_3896_amd.serve import HipExecutor, Server, latency_stats
     torch.cuda.set_device(0)
     cap, maxb = 1 << 20, 256
-    ex = HipExecutor(cap, maxb, "fp32ds")
+    ex = HipExecutor(cap, maxb, args.prec or "fp32ds")
     # saturation: all jobs present at t = 0; throughput over the rounds with a backlog
     sat = serve_requests(inputs.c5_jobs(args.sat_jobs, 0.0, seed=5006))
     for r in sat:
@@ -373,7 +373,7 @@ def bench_c5(args):
         "dtype": "f32",
         "data": "synthetic (seeded Plummer jobs, Poisson arrivals)",
         "config": {"workload": "served stream: N log-uniform [1024,65536], steps U[10,1000], leapfrog/sym6 "
-                               "50/50, galaxy field on half, eps=1e-3, dt=2^-11, fp32ds",
+                               "50/50, galaxy field on half, eps=1e-3, dt=2^-11, " + (args.prec or "fp32ds"),
                    "jobs": args.jobs, "offered_load": args.load, "arrival_rate_per_s": round(rate, 4),
                    "arena_particles": cap, "max_clusters": maxb, "policy": args.policy,
                    "fill": args.fill},
