@@ -59,9 +59,12 @@ def test_accel_ragged_batch_with_field(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32dl"])
-def test_zero_softening_masks_self_term(prec):
+@pytest.mark.parametrize("shape", ["box300", "plummer6000"])
+def test_zero_softening_masks_self_term(prec, shape):
+    """eps = 0: the j = i term is excluded explicitly (potential too); the 6000-particle cluster is
+    split into j-ranges and, in the local mode, has far tiles, so every masked loop runs."""
     torch_dev()
-    p, v, m = inputs.uniform_box(300, 9)
+    p, v, m = inputs.uniform_box(300, 9) if shape == "box300" else inputs.plummer(6000, 31)
     b = inputs.single(p, v, m, 0.0)
     sim = make_sim(b, prec)
     a = sim.accel(pot=True).cpu().numpy()
