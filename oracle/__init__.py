@@ -160,16 +160,17 @@ def total_accel(pos, mass, G=1.0, eps=0.0, field=False, galaxy=None):
     return acc
 
 
-ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M")
+ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M",
+                 "Fx", "Fy", "Fz", "|F|", "sum m|a|", "_")
 
 
 def energy(pos, vel, mass, G=1.0, eps=0.0, field=False, galaxy=None):
-    """Diagnostics of Sect. 5.1 as a 16-vector (layout in ``ENERGY_FIELDS``)."""
+    """Diagnostics of Sect. 5.1 as a 20-vector (layout in ``ENERGY_FIELDS``; F = sum m a_int)."""
     lib = _load()
     pos = _f64(pos)
     n = pos.shape[0]
-    out = np.zeros(16)
-    scratch = np.empty(n)
+    out = np.zeros(20)
+    scratch = np.empty(4 * n)
     lib.oracle_energy(n, _p(pos), _p(_f64(vel)), _p(_f64(mass)), float(G), float(eps), int(bool(field)),
                       _p(_gal(galaxy)), _p(out), _p(scratch))
     return out

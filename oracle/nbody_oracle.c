@@ -12,7 +12,8 @@
  *   - an analytic external field (Sect. 3, Eq. 3 term F_ext): Hernquist bulge + Miyamoto-Nagai
  *     disk + logarithmic halo, closed forms from Binney & Tremaine (the paper names the Allen &
  *     Santillan bulge/disk/halo model without printing it);
- *   - energy, linear and angular momentum and external torque (Sect. 5.1, Eqs. 8-10);
+ *   - energy, linear and angular momentum and external torque (Sect. 5.1, Eqs. 8-10), and the
+ *     mass-weighted sum of the internal accelerations (zero by the antisymmetry of Eq. 2);
  *   - the 2nd-order leapfrog (Sect. 3.1) in kick-drift-kick form and the 6th-order symplectic
  *     integrator of Sect. 3.1 as a 7-stage symmetric composition of leapfrogs (Yoshida 1990,
  *     solution A), with adjacent half-kicks inside one step merged.
@@ -176,25 +177,35 @@ static void total_accel(int64_t n, const double* pos, const double* mass, double
 }
 
 /*
- * Diagnostics of Sect. 5.1 (Eqs. 8-10).  out[16]:
+ * Diagnostics of Sect. 5.1 (Eqs. 8-10), plus the internal force sum of Sect. 2.  out[20]:
  *   0 K = 1/2 sum m v^2        1 W = 1/2 sum m_i phi_i (pairs j != i, softened)
  *   2 Uext = sum m Phi_ext     3 E = K + W + Uext
  *   4..6 P = sum m v           7..9 L = sum m x cross v
  *   10..12 torque = sum m x cross a_ext(x)  (Eq. 8, with F_ext an acceleration as in Eq. 3)
- *   13 M = sum m               14..15 zero
+ *   13 M = sum m
+ *   14..16 F = sum m a_int     (the pair forces of Eq. 2 are antisymmetric, so F = 0 exactly and
+ *                              only rounding remains)
+ *   17 |F|                     18 sum m |a_int|  (the scale |F| is to be compared with)
+ *   19 zero
+ * scratch: 4 n doubles (internal accelerations, then pair potentials).
  */
 void oracle_energy(int64_t n, const double* pos, const double* vel, const double* mass, double G, double eps,
-                   int field, const double* gal, double* out, double* pot_scratch) {
-  oracle_accel(n, pos, mass, G, eps, 0, pot_scratch, 0);
+                   int field, const double* gal, double* out, double* scratch) {
+  double* acc = scratch;
+  double* pot = scratch + 3 * n;
+  oracle_accel(n, pos, mass, G, eps, acc, pot, 0);
   nsum K = {0, 0}, W = {0, 0}, U = {0, 0}, P[3] = {{0, 0}, {0, 0}, {0, 0}}, L[3] = {{0, 0}, {0, 0}, {0, 0}},
-       T[3] = {{0, 0}, {0, 0}, {0, 0}}, M = {0, 0};
+       T[3] = {{0, 0}, {0, 0}, {0, 0}}, M = {0, 0}, F[3] = {{0, 0}, {0, 0}, {0, 0}}, A = {0, 0};
   for (int64_t i = 0; i < n; ++i) {
     const double m = mass[i];
     const double* x = pos + 3 * i;
     const double* v = vel + 3 * i;
+    const double* a = acc + 3 * i;
     nsum_add(&K, 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
-    nsum_add(&W, 0.5 * m * pot_scratch[i]);
+    nsum_add(&W, 0.5 * m * pot[i]);
     for (int c = 0; c < 3; ++c) nsum_add(&P[c], m * v[c]);
+    for (int c = 0; c < 3; ++c) nsum_add(&F[c], m * a[c]);
+    nsum_add(&A, m * sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]));
     nsum_add(&L[0], m * (x[1] * v[2] - x[2] * v[1]));
     nsum_add(&L[1], m * (x[2] * v[0] - x[0] * v[2]));
     nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[0]));
@@ -208,7 +219,7 @@ void oracle_energy(int64_t n, const double* pos, const double* vel, const double
       nsum_add(&T[2], m * (x[0] * ae[1] - x[1] * ae[0]));
     }
   }
-  memset(out, 0, 16 * sizeof(double));
+  memset(out, 0, 20 * sizeof(double));
   out[0] = nsum_get(&K);
   out[1] = nsum_get(&W);
   out[2] = nsum_get(&U);
@@ -217,8 +228,11 @@ void oracle_energy(int64_t n, const double* pos, const double* vel, const double
     out[4 + c] = nsum_get(&P[c]);
     out[7 + c] = nsum_get(&L[c]);
     out[10 + c] = nsum_get(&T[c]);
+    out[14 + c] = nsum_get(&F[c]);
   }
   out[13] = nsum_get(&M);
+  out[17] = sqrt(out[14] * out[14] + out[15] * out[15] + out[16] * out[16]);
+  out[18] = nsum_get(&A);
 }
 
 /*

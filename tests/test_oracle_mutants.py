@@ -26,12 +26,19 @@ MUTANTS = [
     ("disk-z-factor", "G * Md * As / (D3 * s);", "G * Md / (D3 * s);"),
     ("halo-sign", "const double ph = 0.5 * vh * vh * log(r2 + dh * dh);",
      "const double ph = -0.5 * vh * vh * log(r2 + dh * dh);"),
-    ("energy-half-missing", "nsum_add(&W, 0.5 * m * pot_scratch[i]);", "nsum_add(&W, m * pot_scratch[i]);"),
+    ("energy-half-missing", "nsum_add(&W, 0.5 * m * pot[i]);", "nsum_add(&W, m * pot[i]);"),
     ("kinetic-half-missing", "nsum_add(&K, 0.5 * m * (v[0]", "nsum_add(&K, 1.0 * m * (v[0]"),
     ("L-index", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[0]));", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[1]));"),
     ("last-kick-missing", "kick(n, vel, acc, Kc[stages] * dt);", ";"),
     ("bh-power", "G * Mbh / (q2 * sqrt(q2))", "G * Mbh / q2"),
     ("bh-softening-dropped", "const double q2 = r2 + ebh * ebh;", "const double q2 = r2;"),
+    ("torque-sign", "nsum_add(&T[0], m * (x[1] * ae[2] - x[2] * ae[1]));",
+     "nsum_add(&T[0], m * (x[2] * ae[1] - x[1] * ae[2]));"),
+    ("torque-index", "nsum_add(&T[1], m * (x[2] * ae[0] - x[0] * ae[2]));",
+     "nsum_add(&T[1], m * (x[2] * ae[0] - x[0] * ae[1]));"),
+    ("momentum-index", "nsum_add(&P[c], m * v[c]);", "nsum_add(&P[c], m * v[0]);"),
+    ("force-sum-mass-dropped", "nsum_add(&F[c], m * a[c]);", "nsum_add(&F[c], a[c]);"),
+    ("force-abs-mass-dropped", "nsum_add(&A, m * sqrt(", "nsum_add(&A, sqrt("),
 ]
 
 
@@ -101,6 +108,27 @@ def _pins():
     e1 = oracle.energy(p4, v4, m3, 1.0, 0.05)
     if np.abs(e1[7:10] - e0[7:10]).max() > 1e-13 * np.abs(e0[7:10]).max():
         fails.append("L-conservation")
+    # torque against the rotation derivative of U_ext; momentum against the centre-of-mass drift;
+    # the internal force sum (zero, and its two-body magnitude)
+    from test_oracle_energy import off_axis_tracers, rotation_derivative_torque
+    pt, vt, mt = off_axis_tracers()
+    et = oracle.energy(pt, vt, mt, 1.0, 0.01, True)
+    tfd = rotation_derivative_torque(oracle, pt, vt, mt, None)
+    if np.abs(et[10:13] - tfd).max() > 1e-7 * np.abs(tfd).max():
+        fails.append("torque-rotation")
+    p5, v5, m5 = inputs.plummer(32, 31, salpeter=True)
+    v5 = v5 + np.array([0.3, -0.7, 1.1])
+    e5 = oracle.energy(p5, v5, m5, 1.0, 0.02)
+    p6, _, _ = oracle.step(p5, v5, m5, oracle.total_accel(p5, m5, 1.0, 0.02), 1.0 / 64, 16, "leapfrog", 1.0, 0.02)
+    dX = ((m5[:, None] * p6).sum(0) - (m5[:, None] * p5).sum(0)) / 0.25
+    if np.abs(e5[4:7] - dX).max() > 1e-12:
+        fails.append("momentum-centre-of-mass")
+    if not (e5[18] > 0 and e5[17] <= 1e-14 * e5[18]):
+        fails.append("force-sum-zero")
+    e2b = oracle.energy(p2, v2, m2, 1.0, 0.1)
+    r = np.linalg.norm(p2[1] - p2[0])
+    if abs(e2b[18] - 2 * m2[0] * m2[1] * r / (r * r + 0.01) ** 1.5) > 1e-15:
+        fails.append("force-abs-closed-form")
     return fails
 
 
