@@ -8,7 +8,9 @@
  *   - the external field term of Eq. 3 (an analytic bulge + disk + halo galaxy, Sect. 3);
  *   - the kick and drift stages of the 2nd-order leapfrog and of the 6th-order symplectic
  *     composition of Sect. 3.1;
- *   - the energy, momentum, angular momentum and torque diagnostics of Sect. 5.1, Eqs. 8-10.
+ *   - the energy, momentum, angular momentum and torque diagnostics of Sect. 5.1, Eqs. 8-10, and
+ *     the mass-weighted sum of the internal accelerations, which the antisymmetry of the pair
+ *     forces of Eq. 2 makes zero (a check of momentum conservation, Sect. 5.1).
  *
  * Data model
  *   A "system" is a ragged batch of B >= 1 independent clusters (they never interact).  Cluster b
@@ -71,7 +73,8 @@ enum {
   NB_ERR_HIP = -2,         /* a HIP runtime call failed */
   NB_ERR_NOMEM = -3,       /* host-side allocation failed, or workspace too small */
   NB_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
-  NB_ERR_NONFINITE = -5    /* reserved: a diagnostic found a non-finite value */
+  NB_ERR_NONFINITE = -5    /* not returned: nbody_energy is asynchronous and cannot see its own
+                              sums, so it reports non-finite ones in its output (flag out[b][19]) */
 };
 
 enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3, NB_FP32DL = 4 };
@@ -110,7 +113,7 @@ int nbody_create(int device, nbody_ctx** out);
 void nbody_destroy(nbody_ctx* ctx);
 
 /* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
- * nbody_last_error() says why): 8 bytes per particle, plus 32 bytes per particle and j-range
+ * nbody_last_error() says why): 32 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
  * about 2^21/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
  * 512..2^20 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
@@ -133,7 +136,9 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
 
 /* One integrator stage for every cluster b, with per-cluster coefficients (time step folded in):
  *   vel += kick_pre[b] * acc;  pos += drift[b] * vel;  acc = A(pos);  vel += kick_post[b] * acc
- * where A is the acceleration of nbody_accel.  kick_pre, drift, kick_post: HOST arrays [B],
+ * where A is the acceleration of nbody_accel.  This is the kick-drift-kick stage of which both
+ * integrators of Sect. 3.1 are made: the leapfrog is one stage with (dt/2, dt, dt/2); the
+ * 6th-order composition is seven stages with the weights of nbody_sym6_coefficients.  kick_pre, drift, kick_post: HOST arrays [B],
  * finite.  acc must hold A(pos) on entry (first-same-as-last).  This is the unit the
  * continuous-batching server advances each job by; the step functions below are sequences of it.
  * Asynchronous. */
@@ -141,7 +146,8 @@ int nbody_substep(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* 
                   double* acc, const double* kick_pre, const double* drift, const double* kick_post,
                   void* ws, size_t ws_bytes, void* stream);
 
-/* nrounds (1..64) consecutive nbody_substep rounds in one call: coef is a HOST array
+/* nrounds (1..64) consecutive nbody_substep rounds (Sect. 3.1 stages, as above) in one call: coef is
+ * a HOST array
  * [nrounds][B][3] of (kick_pre, drift, kick_post) per round and cluster, all finite.  Round r
  * performs exactly what nbody_substep would with coef[r].  One table upload for all rounds; lets a
  * batching caller chain rounds while the set of clusters does not change.  Asynchronous. */
@@ -169,14 +175,18 @@ int nbody_step_sym6(nbody_ctx* ctx, const nbody_system* sys, double* pos, double
  * host arrays.  Lets a caller drive the same integrator one stage at a time with nbody_substep. */
 int nbody_sym6_coefficients(double* drift7, double* kick8);
 
-/* Diagnostics of Sect. 5.1 per cluster, written to the DEVICE array out[B][16] (float64):
+/* Diagnostics of Sect. 5.1 per cluster, written to the DEVICE array out[B][20] (float64):
  *   0 K = 1/2 sum m |v|^2     1 W = 1/2 sum m_i pot_i     2 Uext = sum m Phi_ext (field clusters)
  *   3 E = K + W + Uext         4..6 P = sum m v             7..9 L = sum m x cross v
  *   10..12 torque = sum m x cross a_ext(x) (Eq. 8)          13 M = sum m
- *   14 0                       15 1.0 if any of the sums is not finite, else 0.0
- * The pair potential is evaluated in the system's precision mode (use NB_FP64 for energy-error
- * measurements).  Reductions run in FP64 in a fixed order (bitwise reproducible).
- * Asynchronous; the non-finite flag is reported in out[b][15] (the call itself cannot see it). */
+ *   14..16 F = sum m a_int     17 |F|                       18 sum m |a_int|
+ *   19 1.0 if any of entries 0..18 is not finite, else 0.0
+ * a_int is the internal (pair) acceleration of Eq. 5 without the galaxy field; the pair forces of
+ * Eq. 2 are antisymmetric, so F is zero up to the rounding of the pair arithmetic, and |F| over
+ * sum m |a_int| measures it.  The pair potential and a_int are evaluated in the system's precision
+ * mode (use NB_FP64 for energy-error measurements).  Reductions run in FP64 in a fixed order
+ * (bitwise reproducible).  Asynchronous: the non-finite flag stands in for NB_ERR_NONFINITE, which
+ * the call cannot return because it does not wait for its kernels. */
 int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* vel,
                  const double* mass, double* out, void* ws, size_t ws_bytes, void* stream);
 

@@ -171,20 +171,26 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Args a) {
   }
 }
 
-// Diagnostics of one chunk (K, W, Uext, P, L, torque, M), then per cluster in the last block.
+// Diagnostics of one chunk, then per cluster in the last block.  Sums (kEnergySums):
+//   0 K  1 W  2 Uext  3-5 P  6-8 L  9-11 torque  12 M  13-15 F = sum m a_int  16 sum m |a_int|
+// where a_int is the internal acceleration and pot_ws the pair potential of the pass before.
+// Output per cluster (kEnergyOut): K, W, Uext, E, P, L, torque, M, F, |F|, sum m |a_int|, and a
+// non-finite flag.
 __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
-  __shared__ double sh[14][kBlock];
+  constexpr int NS = kEnergySums;
+  __shared__ double sh[NS][kBlock];
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
   const int t = threadIdx.x;
-  double q[14];
+  double q[NS];
 #pragma unroll
-  for (int k = 0; k < 14; ++k) q[k] = 0.0;
+  for (int k = 0; k < NS; ++k) q[k] = 0.0;
   if (t < ch.count) {
     const long long i = c.off + ch.start + t;
     const double m = a.mass[i];
     const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
     const double vx = a.vel[3 * i], vy = a.vel[3 * i + 1], vz = a.vel[3 * i + 2];
+    const double ax = a.eacc_ws[3 * i], ay = a.eacc_ws[3 * i + 1], az = a.eacc_ws[3 * i + 2];
     q[0] = 0.5 * m * (vx * vx + vy * vy + vz * vz);
     q[1] = 0.5 * m * a.pot_ws[i];
     q[3] = m * vx;
@@ -194,6 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
     q[7] = m * (z * vx - x * vz);
     q[8] = m * (x * vy - y * vx);
     q[12] = m;
+    q[13] = m * ax;
+    q[14] = m * ay;
+    q[15] = m * az;
+    q[16] = m * sqrt(ax * ax + ay * ay + az * az);
     if (c.flags & kFlagField) {
       double ex, ey, ez;
       galaxy_accel(a.gal, a.G, x, y, z, ex, ey, ez);
@@ -203,34 +213,35 @@ __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
       q[11] = m * (x * ey - y * ex);
     }
   }
-  block_reduce<14>(q, sh);
+  block_reduce<NS>(q, sh);
   if (t == 0) {
 #pragma unroll
-    for (int k = 0; k < 14; ++k) a.epart[(size_t)blockIdx.x * 16 + k] = q[k];
+    for (int k = 0; k < NS; ++k) a.epart[(size_t)blockIdx.x * NS + k] = q[k];
   }
   if (!last_block_of_cluster(&a.chunk_counter[ch.cluster], c.nchunks)) return;
-  double tot[14];
+  double tot[NS];
 #pragma unroll
-  for (int k = 0; k < 14; ++k) tot[k] = 0.0;
+  for (int k = 0; k < NS; ++k) tot[k] = 0.0;
   for (int p = t; p < c.nchunks; p += kBlock) {
-    const double* e = a.epart + (size_t)(c.chunk0 + p) * 16;
+    const double* e = a.epart + (size_t)(c.chunk0 + p) * NS;
 #pragma unroll
-    for (int k = 0; k < 14; ++k) tot[k] += e[k];
+    for (int k = 0; k < NS; ++k) tot[k] += e[k];
   }
   __syncthreads();
-  block_reduce<14>(tot, sh);
+  block_reduce<NS>(tot, sh);
   if (t == 0) {
-    double* o = a.eout + (size_t)ch.cluster * 16;
+    double* o = a.eout + (size_t)ch.cluster * kEnergyOut;
     const double K = tot[0], W = tot[1], U = tot[2];
     o[0] = K;
     o[1] = W;
     o[2] = U;
     o[3] = K + W + U;
-    for (int k = 3; k < 13; ++k) o[k + 1] = tot[k];
-    o[14] = 0.0;
+    for (int k = 3; k < 16; ++k) o[k + 1] = tot[k];  // P, L, torque, M, F
+    o[17] = sqrt(tot[13] * tot[13] + tot[14] * tot[14] + tot[15] * tot[15]);
+    o[18] = tot[16];
     bool finite = true;
-    for (int k = 0; k < 14; ++k) finite = finite && isfinite(o[k]);
-    o[15] = finite ? 0.0 : 1.0;
+    for (int k = 0; k < 19; ++k) finite = finite && isfinite(o[k]);
+    o[19] = finite ? 0.0 : 1.0;
     a.chunk_counter[ch.cluster] = 0;
   }
 }

@@ -71,7 +71,8 @@ __device__ __forceinline__ double4 record64(const Args& a, long long gi) {
   return make_double4(a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], a.mass[gi]);
 }
 
-// Epilogue of one particle: scale by G, add the galaxy field, store, optional kick.
+// Epilogue of one particle: scale by G, add the galaxy field (unless the pass wants the internal
+// acceleration alone), store, optional kick.
 __device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
                                                 double ax, double ay, double az, bool round32, int kick) {
   ax *= a.G;
@@ -82,7 +83,7 @@ __device__ __forceinline__ void finish_particle(const Args& a, const DevCluster&
     ay = (float)ay;
     az = (float)az;
   }
-  if (c.flags & kFlagField) {
+  if ((c.flags & kFlagField) && !a.internal_only) {
     double ex, ey, ez;
     galaxy_accel(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
     ax += ex;

@@ -45,6 +45,10 @@ struct Chunk {
   int cluster, start, count, pad;
 };
 
+// Diagnostics: sums reduced per cluster by the energy pass, and doubles written per cluster.
+constexpr int kEnergySums = 17;
+constexpr int kEnergyOut = 20;
+
 // Pair work item: one i-tile of one cluster against one j-range (js) of it.
 struct PairItem {
   int cluster, i0, js, pad;
@@ -79,8 +83,9 @@ struct Args {
   double* mconst;      // [B] the common mass of a cluster whose masses are all equal, else 0
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
   double4* part;       // partial sums (ax, ay, az, pot) of split clusters
-  double* epart;       // [nchunks * 16] energy partials
+  double* epart;       // [nchunks * kEnergySums] energy partials
   double* pot_ws;      // [Ntot] pair potential scratch for the energy pass
+  double* eacc_ws;     // [Ntot * 3] internal accelerations of the energy pass
   double* coef;        // [B*3] per-cluster (kick_pre, drift, kick_post), or null
   // state
   double* pos;
@@ -88,7 +93,8 @@ struct Args {
   double* acc;
   double* pot;
   const double* mass;
-  double* eout;  // [B*16] energy output
+  double* eout;  // [B * kEnergyOut] energy output
+  int internal_only;  // 1: the pair pass stores the internal acceleration alone (no galaxy field)
   // uniform coefficients (used when coef == null)
   double kick_pre, drift, kick_post;
   double G;

@@ -58,10 +58,11 @@ struct Sym6 {
 };
 const Sym6 kSym6;
 
+
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
-  size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, part, skey, sval, shist,
-      sbase, spos, total;
+  size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, eacc, part, skey, sval,
+      shist, sbase, spos, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -215,9 +216,11 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   L.partials = o;
   o = align_up(o + sizeof(double) * 11 * nchunks);
   L.epart = o;
-  o = align_up(o + sizeof(double) * 16 * nchunks);
+  o = align_up(o + sizeof(double) * kEnergySums * nchunks);
   L.pot = o;
   o = align_up(o + sizeof(double) * ntot);
+  L.eacc = o;
+  o = align_up(o + sizeof(double) * 3 * ntot);
   L.part = o;
   o = align_up(o + sizeof(double4) * npart);
   L.skey = o;  // [2][ntot] (sort tiles present only)
@@ -391,6 +394,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
   a.pot_ws = reinterpret_cast<double*>(w + L.pot);
+  a.eacc_ws = reinterpret_cast<double*>(w + L.eacc);
   a.part = reinterpret_cast<double4*>(w + L.part);
   a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
   a.G = sys->G;
@@ -714,11 +718,14 @@ int64_t nbody_interactions(const nbody_system* sys) {
   return tot;
 }
 
-int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
-                double* pot, void* ws, size_t ws_bytes, void* stream) {
-  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
-  int rc = build_plan(sys, ctx->plan);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+
+// nbody_accel after the plan is built.
+int accel_call(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
+               double* pot, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
   if ((rc = check_state(ctx->plan, pos, nullptr, mass, acc, ws, ws_bytes))) return rc;
   if (pot) {
     if ((rc = check_ptr(pot, "pot"))) return rc;
@@ -738,6 +745,18 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
   P.a.pot = pot;
   P.a.vel = nullptr;
   return evaluate(ctx, P, false, pot != nullptr, false, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
+                double* pot, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  int rc = build_plan(sys, ctx->plan);
+  if (rc) return rc;
+  return accel_call(ctx, sys, pos, mass, acc, pot, ws, ws_bytes, stream);
 }
 
 int nbody_substeps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,
@@ -811,7 +830,7 @@ int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, con
   if ((rc = check_ptr(out, "out"))) return rc;
   if ((rc = check_ptr(vel, "vel"))) return rc;
   if ((rc = check_state(ctx->plan, pos, nullptr, mass, vel, ws, ws_bytes))) return rc;
-  const size_t no = 16 * 8 * (size_t)ctx->plan.B, n3 = 24 * (size_t)ctx->plan.ntot;
+  const size_t no = kEnergyOut * 8 * (size_t)ctx->plan.B, n3 = 24 * (size_t)ctx->plan.ntot;
   if (overlap(out, no, pos, n3) || overlap(out, no, vel, n3) || overlap(out, no, mass, n3 / 3) ||
       overlap(out, no, ws, ctx->plan.L.total))
     return fail(NB_ERR_ARG, "out overlaps another buffer");
@@ -823,7 +842,8 @@ int nbody_energy(nbody_ctx* ctx, const nbody_system* sys, const double* pos, con
   P.a.pos = const_cast<double*>(pos);
   P.a.vel = const_cast<double*>(vel);
   P.a.mass = mass;
-  P.a.acc = nullptr;
+  P.a.acc = P.a.eacc_ws;  // internal accelerations, for the force sums
+  P.a.internal_only = 1;
   P.a.pot = P.a.pot_ws;
   P.a.eout = out;
   if ((rc = evaluate(ctx, P, false, true, false, s))) return rc;

@@ -29,7 +29,9 @@ EXPORTS = (
     "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max",
 )
 
-ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M", "_", "nonfinite")
+ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M",
+                 "Fx", "Fy", "Fz", "|F|", "sum m|a|", "nonfinite")
+ENERGY_WIDTH = len(ENERGY_FIELDS)
 
 
 class NBodyError(RuntimeError):
@@ -317,7 +319,7 @@ class Simulation:
         self.mass = torch.as_tensor(batch.mass, **f64).contiguous()
         self.acc = torch.zeros_like(self.pos)
         self.pot = torch.zeros(self.sys.n, **f64)
-        self.eout = torch.zeros(self.sys.B, 16, **f64)
+        self.eout = torch.zeros(self.sys.B, ENERGY_WIDTH, **f64)
 
     def close(self):
         if self.own_ctx and self.ctx:

@@ -142,7 +142,7 @@ class HipExecutor:
         self.vel = torch.zeros(self.capacity, 3, **f64)
         self.acc = torch.zeros(self.capacity, 3, **f64)
         self.mass = torch.zeros(self.capacity, **f64)
-        self.eout = torch.zeros(self.max_clusters, 16, **f64)
+        self.eout = torch.zeros(self.max_clusters, nbody.ENERGY_WIDTH, **f64)
         self.ws_bytes = self._workspace_bound()
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
         self.ws_addr = (self.ws.data_ptr() + 255) & ~255
@@ -153,7 +153,7 @@ class HipExecutor:
         return nbody.nbody_workspace_bytes_max(self.capacity, self.max_clusters)
 
     def footprint_bytes(self) -> int:
-        return STATE_BYTES_PER_PARTICLE * self.capacity + self.ws_bytes + 16 * 8 * self.max_clusters
+        return STATE_BYTES_PER_PARTICLE * self.capacity + self.ws_bytes + nbody.ENERGY_WIDTH * 8 * self.max_clusters
 
     def close(self):
         if self.ctx:
@@ -366,7 +366,7 @@ class Server:
             if self.energy:
                 e1 = self.ex.energy(a.offset, [a.req.n], [a.req.eps], [a.req.field])[0]
             pos, vel = self.ex.read(a.offset, a.req.n)
-            bad = (not np.all(np.isfinite(pos))) or (not np.all(np.isfinite(vel))) or (e1 is not None and e1[15] != 0)
+            bad = (not np.all(np.isfinite(pos))) or (not np.all(np.isfinite(vel))) or (e1 is not None and e1[19] != 0)
             self.results[a.req.jid] = Result(a.req.jid, "failed" if bad else "done", now_fn() - a.req.arrival, pos,
                                              vel, a.energy0, e1, "non-finite state" if bad else "")
             if self.on_result:

@@ -103,7 +103,29 @@ def test_energy_fp64_matches_oracle():
         scale = np.abs(ref[:4]).max()
         assert np.abs(out[c, :4] - ref[:4]).max() <= 1e-13 * scale + 1e-300
         assert np.abs(out[c, 4:14] - ref[4:14]).max() <= 1e-13 * (np.abs(ref[4:14]).max() + 1e-300)
-        assert out[c, 15] == 0.0
+        # internal force sum: zero up to rounding on both sides, its scale sum m |a_int| to 1e-13
+        assert abs(out[c, 18] - ref[18]) <= 1e-13 * ref[18] + 1e-300
+        assert np.abs(out[c, 14:18]).max() <= 1e-14 * ref[18] + 1e-300
+        assert out[c, 19] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ds", "fp32dl", "fp32c"])
+def test_energy_internal_force_sum(prec):
+    """sum m a_int = 0 (antisymmetry of the Eq. 2 pair forces): |F| / sum m |a_int| is at the
+    rounding level of the mode's pair arithmetic, and sum m |a_int| matches the oracle's."""
+    torch_dev()
+    b = _ragged_batch(seed=11, sizes=(2, 255, 700, 3000, 9000))
+    sim = make_sim(b, prec)
+    out = sim.energy().cpu().numpy()
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    for c in range(b.B):
+        s, e = b.offsets[c], b.offsets[c + 1]
+        ref = oracle.energy(b.pos[s:e], b.vel[s:e], b.mass[s:e], b.G, b.eps[c], bool(b.field[c]), b.galaxy)
+        print("\n[force sum %s N=%d] |F|/sum m|a| gpu %.2e oracle %.2e" % (
+            prec, e - s, out[c, 17] / out[c, 18], ref[17] / ref[18]), flush=True)
+        assert out[c, 17] <= tol * out[c, 18]
+        assert abs(out[c, 17] - np.linalg.norm(out[c, 14:17])) <= 1e-15 * out[c, 17] + 1e-300
+        assert abs(out[c, 18] - ref[18]) <= tol * ref[18]
 
 
 def test_energy_flags_nonfinite():
@@ -113,7 +135,7 @@ def test_energy_flags_nonfinite():
     b = inputs.concat([inputs.single(p, v, m, 1e-3), inputs.single(*inputs.plummer(100, 3), 1e-3)])
     sim = make_sim(b, "fp64")
     out = sim.energy().cpu().numpy()
-    assert out[0, 15] == 1.0 and out[1, 15] == 0.0
+    assert out[0, 19] == 1.0 and out[1, 19] == 0.0
 
 
 def test_leapfrog_trajectory_c1_fp64():
