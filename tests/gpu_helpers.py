@@ -3,18 +3,22 @@ the oracle on the same seeded inputs."""
 import numpy as np
 
 import oracle
+from paper_1003_3896_amd import accuracy
 
-# Tolerances on err_i = |a_gpu,i - a_ref,i| / S_i, with S_i = G sum_j m_j |d_ij| / (d^2+eps^2)^{3/2}
-# + |a_ext,i| (the sum of the magnitudes of every term of particle i's acceleration).
-#   FP64: ~20 FP64 roundings per term                              -> 1e-12 (observed ~1e-16)
+# Gates on err_i = |a_gpu,i - a_ref,i| / S_i, S_i = G sum_j m_j |d_ij| / (d^2+eps^2)^{3/2} + |a_ext,i|
+# (the sum of the magnitudes of every term of particle i's acceleration), from accuracy.S_MAX and
+# accuracy.S_MEDIAN:
+#   FP64: ~20 FP64 roundings per term                              -> max 1e-12 (observed ~1e-16)
 #   FP32DS: differences exact to fl32 of the difference; r^2, rsq, the cube and the product add
-#   ~8 FP32 roundings (2^-24 each) per term, tile sums folded into FP64 -> 1e-6
-#   FP32C: as FP32DS plus the rounding of the centred coordinates themselves, which perturbs a
-#   pair term by ~2^-24 |x| / |d| (unbounded for close pairs) -> gated on the median only
-#   FP32DL: far j-tiles have coordinate differences within 1.5 x 2^-22 relative (local centring), near
-#   ones are double-single -> 1e-6 as FP32DS
-TOL = {"fp64": 1e-12, "fp32ds": 1e-6, "fp32dl": 1e-6}
-TOL_MEDIAN = {"fp64": 1e-14, "fp32ds": 1e-7, "fp32c": 1e-6, "fp32dl": 1e-7}
+#   ~8 FP32 roundings (2^-24 each) per term, tile sums folded into FP64 -> max 1e-6
+#   FP32DL: far j-tiles have coordinate differences within 1.5 x 2^-22 relative (local centring),
+#   near ones are double-single -> max 1e-6 as FP32DS
+#   FP32C: as FP32DS plus the rounding of the centred coordinates themselves, which perturbs a pair
+#   term by ~2^-24 |x| / |d| (unbounded for close pairs) -> median 1e-6, max 1e-3 (a sanity gate
+#   that catches a wrong sign, mass or G, not an accuracy claim)
+#   FP32: absolute FP32 coordinates and one FP32 sum -> median 1e-6, max 1e-3 (sanity gate)
+TOL = accuracy.S_MAX
+TOL_MEDIAN = accuracy.S_MEDIAN
 
 
 def torch_dev():
@@ -50,12 +54,7 @@ def oracle_reference(batch, want_pot=False):
 
 
 def rel_errors(a_gpu, a_ref, scale):
-    d = np.linalg.norm(np.asarray(a_gpu) - a_ref, axis=1)
-    out = np.zeros_like(d)
-    nz = scale > 0
-    out[nz] = d[nz] / scale[nz]
-    out[~nz] = np.where(d[~nz] == 0, 0.0, np.inf)
-    return out
+    return accuracy.s_errors(a_gpu, a_ref, scale)
 
 
 def stats(err):
