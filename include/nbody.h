@@ -105,7 +105,10 @@ typedef struct {
 } nbody_system;
 
 /* Create a context bound to HIP device `device` (>= 0).  The context caches launch plans and
- * tile choices; it owns a small pinned host staging area and never allocates device memory.
+ * tile choices; it owns a small pinned host staging area (NB_NOALLOC_TABLE_BYTES for the
+ * no-allocation entry point, plus a ring that grows with the tables of the other calls) and never
+ * allocates device memory.  It also looks up the device's copy of the static scratch of
+ * nbody_accel_noalloc (the first context on a device loads the library's code objects there).
  * Returns NB_ERR_ARG for a bad device or NULL out, NB_ERR_HIP if the device cannot be used. */
 int nbody_create(int device, nbody_ctx** out);
 
@@ -133,6 +136,25 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters);
  * stream: a hipStream_t (NULL = the default stream).  Asynchronous. */
 int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass,
                 double* acc, double* pot, void* ws, size_t ws_bytes, void* stream);
+
+/* nbody_accel without a caller workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).  The workspace
+ * is a static device array of NB_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from
+ * the library's first use on that GPU until the process ends; the tables go up through a pinned
+ * staging buffer of NB_NOALLOC_TABLE_BYTES that nbody_create allocated.  The call itself allocates
+ * nothing (no hipMalloc, hipFree or pinned allocation).  Same arguments, results and errors as
+ * nbody_accel, and bitwise the same accelerations and potentials.  Limits: a system whose
+ * nbody_workspace_bytes exceeds NB_NOALLOC_SCRATCH_BYTES (a single cluster of more than about 4.0
+ * million particles, 1.6 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
+ * than about 42,000 clusters) returns NB_ERR_ARG; these two checks run first and need
+ * neither a context nor a GPU.  Every call on one GPU shares that GPU's scratch, which keeps the
+ * last call's contents (the per-call counters are cleared by the call's own table upload): calls
+ * that overlap on one GPU (several streams, threads or contexts at once) race and give wrong
+ * results, so order them on one stream.  Asynchronous. */
+#define NB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+#define NB_NOALLOC_TABLE_BYTES ((size_t)4 << 20)
+int nbody_accel_noalloc(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass,
+                        double* acc, double* pot, void* stream);
 
 /* One integrator stage for every cluster b, with per-cluster coefficients (time step folded in):
  *   vel += kick_pre[b] * acc;  pos += drift[b] * vel;  acc = A(pos);  vel += kick_post[b] * acc

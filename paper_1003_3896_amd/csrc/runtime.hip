@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +59,17 @@ struct Sym6 {
 };
 const Sym6 kSym6;
 
+// Scratch of the no-allocation entry point (nbody_accel_noalloc): a fixed array in this source's
+// code object, so each GPU the library runs on holds its own copy from module load until the
+// process ends.  Host code must never pass `scratch` itself to a kernel or copy (on the host the
+// name is a stand-in, not a device address): the address of each device's copy is looked up once
+// per device with hipGetSymbolAddress and kept in g_scratch.
+constexpr size_t kScratchBytes = NB_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kScratchTableBytes = NB_NOALLOC_TABLE_BYTES;  // pinned staging of its tables
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
 
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
@@ -120,6 +132,8 @@ struct StepGraph {
 
 struct nbody_ctx {
   int device = 0;
+  void* scratch = nullptr;  // device address of this device's copy of `scratch`
+  Slot fixed;               // pinned staging of the no-allocation entry point, allocated at creation
   int cus = 256;
   bool graphs = false;
   hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
@@ -342,8 +356,28 @@ struct Prepared {
   bool centred = false;
 };
 
+// The context's preallocated staging slot for `bytes` of tables: waits for its previous copy, never
+// allocates (the no-allocation entry point's path).
+Slot* fixed_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
+  Slot& s = ctx->fixed;
+  *rc = NB_OK;
+  if (!s.host || bytes > s.cap) {
+    *rc = fail(NB_ERR_ARG, "tables of %zu bytes exceed the %zu-byte staging buffer", bytes, s.cap);
+    return nullptr;
+  }
+  if (s.used) {
+    hipError_t e = hipEventSynchronize(s.ev);
+    if (e != hipSuccess) {
+      *rc = fail(NB_ERR_HIP, "staging wait: %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    s.used = false;
+  }
+  return &s;
+}
+
 int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, const double* coef3,
-            Prepared& P, hipStream_t stream, int rounds = 1) {
+            Prepared& P, hipStream_t stream, int rounds = 1, bool fixed = false) {
   Plan& p = ctx->plan;
   const int fam = family_of(sys->prec);
   const TileCfg t = ctx->tiles[fam][size_class(p.maxn)];
@@ -361,7 +395,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   memcpy(blob.data() + L.items, items.data(), sizeof(PairItem) * items.size());
   if (coef3) memcpy(blob.data() + L.coef, coef3, coef_bytes);
   int rc = NB_OK;
-  Slot* s = get_slot(ctx, up, &rc);
+  Slot* s = fixed ? fixed_slot(ctx, up, &rc) : get_slot(ctx, up, &rc);
   if (!s) return rc;
   memcpy(s->host, blob.data(), up);
   HIP_TRY(hipMemcpyAsync(ws, s->host, up, hipMemcpyHostToDevice, stream));
@@ -658,16 +692,47 @@ int nbody_create(int device, nbody_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     ctx->cus = cus;
   default_tiles(ctx);
+  // set-up of the no-allocation entry point: this device's scratch address (once per device, with
+  // the device current) and the context's own pinned staging buffer
+  {
+    DeviceGuard g(device);
+    int rc = NB_OK;
+    if (!g.ok) rc = fail(NB_ERR_HIP, "cannot select device %d", device);
+    if (!rc && device >= kMaxDevices) rc = fail(NB_ERR_UNSUPPORTED, "device %d: at most %d devices", device, kMaxDevices);
+    if (!rc) {
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+          rc = fail(NB_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        else
+          g_scratch[device] = ptr;
+      }
+      ctx->scratch = g_scratch[device];
+    }
+    if (!rc && hipHostMalloc(&ctx->fixed.host, kScratchTableBytes, hipHostMallocDefault) != hipSuccess) {
+      ctx->fixed.host = nullptr;
+      rc = fail(NB_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", kScratchTableBytes);
+    }
+    if (!rc) ctx->fixed.cap = kScratchTableBytes;
+    if (!rc && hipEventCreateWithFlags(&ctx->fixed.ev, hipEventDisableTiming) != hipSuccess)
+      rc = fail(NB_ERR_HIP, "hipEventCreate failed");
+    if (rc) {
+      nbody_destroy(ctx);
+      return rc;
+    }
+  }
   *out = ctx;
   return NB_OK;
 }
 
 void nbody_destroy(nbody_ctx* ctx) {
   if (!ctx) return;
-  for (Slot& s : ctx->slots) {
-    if (s.used && s.ev) (void)hipEventSynchronize(s.ev);
-    if (s.ev) (void)hipEventDestroy(s.ev);
-    if (s.host) (void)hipHostFree(s.host);
+  for (Slot* s : {&ctx->slots[0], &ctx->slots[1], &ctx->slots[2], &ctx->slots[3], &ctx->fixed}) {
+    if (s->used && s->ev) (void)hipEventSynchronize(s->ev);
+    if (s->ev) (void)hipEventDestroy(s->ev);
+    if (s->host) (void)hipHostFree(s->host);
   }
   for (auto& pr : ctx->pending) {
     (void)hipEventSynchronize(pr.second);
@@ -722,9 +787,10 @@ int64_t nbody_interactions(const nbody_system* sys) {
 
 namespace {
 
-// nbody_accel after the plan is built.
+// nbody_accel after the plan is built: the caller's workspace, or the static scratch with the
+// context's preallocated staging buffer (fixed).
 int accel_call(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
-               double* pot, void* ws, size_t ws_bytes, void* stream) {
+               double* pot, void* ws, size_t ws_bytes, void* stream, bool fixed) {
   int rc;
   if ((rc = check_state(ctx->plan, pos, nullptr, mass, acc, ws, ws_bytes))) return rc;
   if (pot) {
@@ -738,7 +804,7 @@ int accel_call(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const
   if (!g.ok) return fail(NB_ERR_HIP, "cannot select device %d", ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Prepared P;
-  if ((rc = prepare(ctx, sys, ws, ws_bytes, nullptr, P, s))) return rc;
+  if ((rc = prepare(ctx, sys, ws, ws_bytes, nullptr, P, s, 1, fixed))) return rc;
   P.a.pos = const_cast<double*>(pos);
   P.a.mass = mass;
   P.a.acc = acc;
@@ -756,7 +822,25 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
   if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
   int rc = build_plan(sys, ctx->plan);
   if (rc) return rc;
-  return accel_call(ctx, sys, pos, mass, acc, pot, ws, ws_bytes, stream);
+  return accel_call(ctx, sys, pos, mass, acc, pot, ws, ws_bytes, stream, false);
+}
+
+int nbody_accel_noalloc(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass, double* acc,
+                        double* pot, void* stream) {
+  // the limits are host-only checks of the system, made before anything else
+  Plan local;
+  Plan& p = ctx ? ctx->plan : local;
+  int rc = build_plan(sys, p);
+  if (rc) return rc;
+  if (p.L.total > kScratchBytes)
+    return fail(NB_ERR_ARG, "the system needs %zu bytes of workspace; the no-allocation scratch holds %zu",
+                p.L.total, kScratchBytes);
+  if (p.L.blob > kScratchTableBytes)
+    return fail(NB_ERR_ARG, "the system's tables take %zu bytes; the no-allocation staging buffer holds %zu",
+                p.L.blob, kScratchTableBytes);
+  if (!ctx) return fail(NB_ERR_ARG, "context is NULL");
+  if (!ctx->scratch) return fail(NB_ERR_HIP, "device scratch address unknown");
+  return accel_call(ctx, sys, pos, mass, acc, pot, ctx->scratch, kScratchBytes, stream, true);
 }
 
 int nbody_substeps(nbody_ctx* ctx, const nbody_system* sys, double* pos, double* vel, const double* mass,

@@ -26,8 +26,11 @@ EXPORTS = (
     "nbody_create", "nbody_destroy", "nbody_workspace_bytes", "nbody_accel", "nbody_substep",
     "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_last_error", "nbody_set_tile",
     "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions", "nbody_use_graphs",
-    "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max",
+    "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max", "nbody_accel_noalloc",
 )
+# limits of nbody_accel_noalloc (NB_NOALLOC_SCRATCH_BYTES, NB_NOALLOC_TABLE_BYTES in include/nbody.h)
+NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_TABLE_BYTES = 4 << 20
 
 ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M",
                  "Fx", "Fy", "Fz", "|F|", "sum m|a|", "nonfinite")
@@ -86,6 +89,7 @@ def lib():
         L.nbody_workspace_bytes_max.argtypes = [I64, I32]
         L.nbody_workspace_bytes_max.restype = SZ
         L.nbody_accel.argtypes = [P, SYS, P, P, P, P, P, SZ, P]
+        L.nbody_accel_noalloc.argtypes = [P, SYS, P, P, P, P, P]
         L.nbody_substep.argtypes = [P, SYS, P, P, P, P, P, P, P, P, SZ, P]
         L.nbody_substeps.argtypes = [P, SYS, P, P, P, P, P, I32, P, SZ, P]
         L.nbody_step_leapfrog.argtypes = [P, SYS, P, P, P, P, D, I32, P, SZ, P]
@@ -100,7 +104,7 @@ def lib():
         L.nbody_timing_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
         L.nbody_interactions.argtypes = [SYS]
         L.nbody_interactions.restype = I64
-        for name in ("nbody_create", "nbody_accel", "nbody_substep", "nbody_step_leapfrog", "nbody_step_sym6",
+        for name in ("nbody_create", "nbody_accel", "nbody_accel_noalloc", "nbody_substep", "nbody_step_leapfrog", "nbody_step_sym6",
                      "nbody_energy", "nbody_set_tile", "nbody_get_tile", "nbody_timing_enable", "nbody_use_graphs",
                      "nbody_sym6_coefficients", "nbody_substeps",
                      "nbody_timing_read"):
@@ -210,6 +214,12 @@ def nbody_interactions(sys: System) -> int:
 def nbody_accel(ctx, sys: System, pos, mass, acc, pot, ws, ws_bytes: int, stream=None) -> None:
     _check(lib().nbody_accel(ctx, sys.ref(), _addr(pos), _addr(mass), _addr(acc), _addr(pot), _addr(ws),
                              int(ws_bytes), _stream(stream)))
+
+
+def nbody_accel_noalloc(ctx, sys: System, pos, mass, acc, pot, stream=None) -> None:
+    """nbody_accel with the library's static device scratch instead of a caller workspace."""
+    _check(lib().nbody_accel_noalloc(ctx, sys.ref(), _addr(pos), _addr(mass), _addr(acc), _addr(pot),
+                                     _stream(stream)))
 
 
 def nbody_substep(ctx, sys: System, pos, vel, mass, acc, kick_pre, drift, kick_post, ws, ws_bytes: int,
