@@ -13,8 +13,14 @@ Prints ONE JSON line.  Besides the contract fields it carries:
                 the stream the kernel runs on, over the timed region;
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample of the same
                 workload (a block of rows against all N sources);
-  modes         the same step timed in the other precision modes.
-Other workloads (--workload c1|c2|c4) run their own configurations.
+  modes         the same step timed in the other precision modes;
+  accel_error_on_fp64_trajectory  every mode's accuracy (paper_1003_3896_amd.accuracy: the a_rms,
+                per-particle, L2 and S_i metrics) on states of the FP64 trajectory;
+  c1, c2, c4, c5  short runs of the other configurations (default run only; --no-extras skips
+                them): C1 with step graphs on and off, the C2 step with its accuracy on the state
+                after 50 FP64 sym6 steps, the C4 ensemble batched against per-cluster launches, and a
+                bounded C5 served stream with p50/p99 latency beside its throughput.
+Other workloads (--workload c1|c2|c4|c5|paper|bh) run their own configurations in full.
 """
 import argparse
 import hashlib
@@ -52,6 +58,8 @@ def parse():
     ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="c3: skip the c1/c2/c4/c5 keys")
+    ap.add_argument("--extra-jobs", type=int, default=120, help="c3 extras: jobs of the bounded C5 stream")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -76,7 +84,12 @@ def workload(name):
 ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
 
 
-PROFILE_TAG = {"c3": "plummer262144", "c2": "salpeter65536"}  # workloads with a committed counter summary
+PROFILE_TAG = {"c3": "plummer262144", "c2": "salpeter65536", "c4": "ensemble512"}  # committed counter summaries
+# issue model of the FP32 pair loop on gfx950 (measured, without packed FP32): an FP32 VALU
+# instruction every 2.45 SIMD cycles with dual issue across waves, a transcendental 16 cycles inside a
+# VALU stream (8 when two waves' transcendentals pair); a wave-interaction is 20 cycles at peak
+ISSUE_VALU_CYCLES = 2.45
+ISSUE_TRANS_CYCLES = (16.0, 8.0)
 # sources that decide what a pair-kernel launch does (its code, work items and split rule)
 PAIR_SOURCES = [os.path.join(ROOT, "paper_1003_3896_amd", "csrc", f)
                 for f in ("pair_kernel.h", "nb_device.h", "nb_internal.h", "runtime.hip")]
@@ -123,6 +136,22 @@ def traffic_from_profile(prec, tile=None, workload="c3"):
         return float(f["hbm_bytes_per_launch"]) if f else None
     except (KeyError, ValueError):
         return None
+
+
+def issue_model(prec, tile=None, workload="c3"):
+    """The issue-model ceiling of the pair kernel from the committed counter summary (VALU and
+    transcendental instructions per wave-interaction), or None."""
+    f = profile_summary(prec, tile, workload)
+    try:
+        valu, trans = float(f["valu_per_wave_interaction"]), float(f["trans_per_wave_interaction"])
+    except (TypeError, KeyError, ValueError):
+        return None
+    cyc = [valu * ISSUE_VALU_CYCLES + trans * t for t in ISSUE_TRANS_CYCLES]
+    return {"valu_per_wave_interaction": valu, "trans_per_wave_interaction": trans,
+            "ceiling_frac_trans_unpaired": round(20.0 / cyc[0], 4),
+            "ceiling_frac_trans_paired": round(20.0 / cyc[1], 4),
+            "model": "20 cycles per wave-interaction at peak; VALU %.2f cycles, transcendental %g (unpaired) or "
+                     "%g (paired); packed FP32 not used" % (ISSUE_VALU_CYCLES, *ISSUE_TRANS_CYCLES)}
 
 
 def time_steps(sim, integrator, dt, steps, warmup, torch):
@@ -245,63 +274,195 @@ def _cpu_model():
     return "unknown"
 
 
-def mode_errors(batch, accel_init, nrows):
-    """Error of every precision mode's first force evaluation against the oracle on the first nrows
-    particles of the first cluster (initial state): err_i = |a_i - a_ref,i| / S_i as in the tests."""
-    import numpy as np
+def sample_rows(n, nrows):
+    """About nrows rows of a cluster of n, in three blocks: its start, middle and end."""
+    if nrows >= n:
+        return np.arange(n)
+    per = max(1, nrows // 3)
+    h = n // 2
+    blocks = [(0, per), (max(per, h - per // 2), max(per, h - per // 2) + per), (max(0, n - per), n)]
+    idx = np.unique(np.concatenate([np.arange(a, min(b, n)) for a, b in blocks]))
+    return idx
+
+
+def oracle_rows(batch, pos, idx):
+    """Oracle acceleration (internal + field) and S_i of rows idx of the first cluster at pos."""
     import oracle
     n = int(batch.offsets[1])
-    ref, absa = oracle.accel(batch.pos[:n], batch.mass[:n], batch.G, float(batch.eps[0]), rows=(0, nrows),
-                             want_abs=True)
-    if batch.field[0]:
-        ae, _ = oracle.ext_field(batch.pos[:nrows], batch.G, batch.galaxy)
-        ref = ref + ae
-        absa = absa + np.linalg.norm(ae, axis=1)
-    return {m: _err_stats(a, ref, absa) for m, a in accel_init.items()}
+    refs, scales = [], []
+    # contiguous runs of idx, one oracle call each
+    cuts = np.nonzero(np.diff(idx) != 1)[0] + 1
+    for run in np.split(idx, cuts):
+        r0, r1 = int(run[0]), int(run[-1]) + 1
+        ref, absa = oracle.accel(pos[:n], batch.mass[:n], batch.G, float(batch.eps[0]), rows=(r0, r1),
+                                 want_abs=True)
+        if batch.field[0]:
+            ae, _ = oracle.ext_field(pos[r0:r1], batch.G, batch.galaxy)
+            ref = ref + ae
+            absa = absa + np.linalg.norm(ae, axis=1)
+        refs.append(ref)
+        scales.append(absa)
+    return np.concatenate(refs), np.concatenate(scales)
 
 
-def _err_stats(a, ref, absa):
-    """err_i = |a_i - a_ref,i| / S_i (max, median) and max_i |a_i - a_ref,i| / a_rms of the rows."""
-    import numpy as np
-    d = np.linalg.norm(a - ref, axis=1)
-    arms = float(np.sqrt(np.mean(np.sum(ref * ref, axis=1))))
-    err = d / absa
-    return {"rows": int(a.shape[0]), "max": float(err.max()), "median": float(np.median(err)),
-            "max_over_arms": float(d.max() / arms)}
-
-
-def sampled_state_errors(batch, modes, integrator, dt, steps, nrows, torch):
-    """Accuracy of every mode's force evaluation on states of the FP64-mode trajectory (steps 0,
-    steps/2 and steps), each against the oracle on the same state (first nrows particles of the
-    first cluster)."""
-    import numpy as np
-    import oracle
-    from paper_1003_3896_amd import nbody
+def sampled_state_errors(batch, modes, integrator, dt, targets, nrows, torch):
+    """Accuracy of every mode's force evaluation on states of the FP64-mode trajectory (after each
+    step count in targets), against the oracle on the same state, on sampled rows of the first
+    cluster; a_rms from the library's FP64 evaluation of the whole cluster (pinned to the oracle by
+    the tests).  All metrics of paper_1003_3896_amd.accuracy."""
+    from paper_1003_3896_amd import accuracy, nbody
     n = int(batch.offsets[1])
+    idx = sample_rows(n, nrows)
     ref_sim = nbody.Simulation(batch, "fp64")
     ref_sim.accel()
     sims = {m: nbody.Simulation(batch, m) for m in modes}
     out, done = {}, 0
-    for target in sorted({0, steps // 2, steps}):
+    for target in sorted(set(targets)):
         if target > done:
             ref_sim.step(integrator, dt, target - done)
             done = target
         torch.cuda.synchronize()
         pos = ref_sim.pos.cpu().numpy()
-        ref, absa = oracle.accel(pos[:n], batch.mass[:n], batch.G, float(batch.eps[0]), rows=(0, nrows),
-                                 want_abs=True)
-        if batch.field[0]:
-            ae, _ = oracle.ext_field(pos[:nrows], batch.G, batch.galaxy)
-            ref = ref + ae
-            absa = absa + np.linalg.norm(ae, axis=1)
+        a64 = ref_sim.acc.cpu().numpy()[:n]
+        arms = [float(np.sqrt(np.mean((a64 * a64).sum(1))))]
+        ref, scale = oracle_rows(batch, pos, idx)
         row = {}
-        for m, s in sims.items():
-            s.pos.copy_(ref_sim.pos)
-            row[m] = _err_stats(s.accel().cpu().numpy()[:nrows], ref, absa)
+        for m, sm in sims.items():
+            sm.pos.copy_(ref_sim.pos)
+            a = sm.accel().cpu().numpy()[idx]
+            row[m] = accuracy.short(accuracy.accel_error(a, ref, offsets=[0, n], scale=scale, rows=idx, arms=arms))
         out[str(target)] = row
-    for s in list(sims.values()) + [ref_sim]:
-        s.close()
+    for sm in list(sims.values()) + [ref_sim]:
+        sm.close()
     return out
+
+
+def graph_ab(batch, prec, integrator, dt, steps, torch):
+    """Wall-clock ms per step of the same run with step graphs on and off (no per-kernel events)."""
+    from paper_1003_3896_amd import nbody
+    gres = {}
+    for use in (True, False):
+        s3 = nbody.Simulation(batch, prec)
+        nbody.nbody_use_graphs(s3.ctx, use)
+        s3.accel()
+        s3.step(integrator, dt, steps)  # the same call as the timed one: graphs captured here
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s3.step(integrator, dt, steps)
+        torch.cuda.synchronize()
+        gres["graphs_on" if use else "graphs_off"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
+        s3.close()
+    return gres
+
+
+def pair_roofline(prec, inter_per_eval, pair_ms, tile=None, workload="c3"):
+    achieved = FLOPS_PER_INTERACTION * inter_per_eval / (pair_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic_from_profile(prec, tile, workload),
+            "kernel": "pair (%s)" % prec, "kernel_ms": round(pair_ms, 4)}
+
+
+def extra_c1(torch):
+    """C1 (N = 1024 Plummer, FP64, 100 leapfrog steps of 1/1024): launch-bound; graphs on and off."""
+    from paper_1003_3896_amd import inputs, nbody
+    b = inputs.c1()
+    sim = nbody.Simulation(b, "fp64")
+    wall, kms, nl = time_steps(sim, "leapfrog", b.meta["dt"], 100, 3, torch)
+    sim.close()
+    return {"workload": "plummer-1024, fp64, leapfrog, 100 steps", "ms_per_step": round(wall / 100 * 1e3, 4),
+            "G_interactions_per_s": round(b.n * b.n * 100 / wall / 1e9, 3),
+            "pair_kernel_ms": round(kms / max(nl, 1), 4),
+            "ms_per_step_graphs": graph_ab(b, "fp64", "leapfrog", b.meta["dt"], 100, torch)}
+
+
+def extra_c2(torch, steps=5):
+    """C2 (N = 65536 Salpeter + galaxy, sym6): a few whole steps in the local double-single mode, and
+    every FP32 mode's accuracy on the state after 50 FP64 sym6 steps."""
+    from paper_1003_3896_amd import autotune, inputs, nbody
+    b = inputs.c2()
+    prec = "fp32dl"
+    dt = b.meta["dt"]
+    sim = nbody.Simulation(b, prec)
+    tile = nbody.nbody_get_tile(sim.ctx, prec, autotune.size_class(b.n))
+    e0 = energy_fp64(sim)
+    wall, kms, nl = time_steps(sim, "sym6", dt, steps, 1, torch)
+    e1 = energy_fp64(sim)
+    sim.close()
+    ipe = b.interactions_per_eval()
+    out = {"workload": "plummer-salpeter-65536, galaxy field, sym6, dt 2^-11", "precision_mode": prec,
+           "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4),
+           "G_interactions_per_s": round(ipe * 7 * steps / wall / 1e9, 3),
+           "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c2"),
+           "energy": dict(drift_report(e0, e1), steps=steps + 1)}
+    out["accel_error_after_50_fp64_steps"] = sampled_state_errors(
+        b, ["fp32dl", "fp32ds", "fp32c"], "sym6", dt, [50], 768, torch)["50"]
+    return out
+
+
+def c4_accuracy(batch, torch):
+    """The batched launch and single-cluster launches of the same clusters (smallest, largest, two
+    in between) against the oracle: the accuracy the throughput comparison is made at."""
+    import oracle
+    from paper_1003_3896_amd import accuracy, inputs, nbody
+    sizes = np.diff(batch.offsets)
+    order = np.argsort(sizes, kind="stable")
+    pick = sorted({int(order[0]), int(order[-1]), int(order[len(order) // 3]), int(order[2 * len(order) // 3])})
+    sim = nbody.Simulation(batch, "fp32ds")
+    a_b = sim.accel().cpu().numpy()
+    sim.close()
+    got = {"batched": [], "per_cluster": []}
+    refs, scales = [], []
+    for c in pick:
+        s, e = int(batch.offsets[c]), int(batch.offsets[c + 1])
+        ref, absa = oracle.accel(batch.pos[s:e], batch.mass[s:e], batch.G, float(batch.eps[c]), want_abs=True)
+        refs.append(ref)
+        scales.append(absa)
+        got["batched"].append(a_b[s:e])
+        one = nbody.Simulation(inputs.single(batch.pos[s:e], batch.vel[s:e], batch.mass[s:e], batch.eps[c]), "fp32ds")
+        got["per_cluster"].append(one.accel().cpu().numpy())
+        one.close()
+    offs = np.concatenate([[0], np.cumsum([len(r) for r in refs])])
+    ref, scale = np.concatenate(refs), np.concatenate(scales)
+    out = {k: accuracy.short(accuracy.accel_error(np.concatenate(v), ref, offsets=offs, scale=scale))
+           for k, v in got.items()}
+    out["clusters"] = [int(sizes[c]) for c in pick]
+    return out
+
+
+def extra_c4(torch, steps=3, base_steps=2):
+    """C4 (512 Plummer clusters, 256..16384, sym6, FP32DS): the persistent ragged launch against the
+    same kernels launched cluster by cluster, a few steps each, and their accuracy."""
+    from paper_1003_3896_amd import autotune, inputs, nbody
+    b = inputs.c4()
+    prec = "fp32ds"
+    dt = b.meta["dt"]
+    sim = nbody.Simulation(b, prec)
+    tile = nbody.nbody_get_tile(sim.ctx, prec, autotune.size_class(int(np.diff(b.offsets).max())))
+    wall, kms, nl = time_steps(sim, "sym6", dt, steps, 1, torch)
+    sim.close()
+    ipe = b.interactions_per_eval()
+    value = ipe * 7 * steps / wall / 1e9
+    el = per_cluster_baseline(b, "sym6", dt, base_steps, torch)
+    per = ipe * 7 * base_steps / el / 1e9
+    return {"workload": "512 Plummer clusters, N log-uniform [256,16384], eps 1e-3, sym6", "precision_mode": prec,
+            "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4), "G_interactions_per_s": round(value, 3),
+            "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c4"),
+            "per_cluster_launches": {"G_interactions_per_s": round(per, 3), "steps": base_steps,
+                                     "ms_per_step": round(el / base_steps * 1e3, 4)},
+            "batched_over_per_cluster": round(value / per, 2),
+            "accel_error": c4_accuracy(b, torch)}
+
+
+def extra_c5(args):
+    """A bounded C5 served stream (the full stream is --workload c5)."""
+    import argparse
+    a = argparse.Namespace(**vars(args))
+    a.jobs, a.sat_jobs, a.prec, a.load, a.policy, a.fill = args.extra_jobs, 32, "fp32ds", 0.8, "srpt", 2.0 ** 30
+    r = bench_c5(a)
+    keep = ("value", "unit", "latency_s", "stretch", "saturation_G_interactions_per_s", "rounds", "jobs_done",
+            "jobs_failed", "max_rel_energy_error", "config")
+    return {k: r[k] for k in keep}
 
 
 def serve_requests(jobs):
@@ -487,7 +648,7 @@ def bench_black_hole(args):
                "dE_over_E0": float(abs(e1[3] - e0[3]) / abs(e0[3])),
                "dL_over_L0": float(np.linalg.norm(L1 - L0) / np.linalg.norm(L0)),
                "dLz_over_Lz0": float(abs(L1[2] - L0[2]) / abs(L0[2])),
-               "ms_per_step": round(wall / steps * 1e3, 4), "finite": bool(e1[15] == 0)}
+               "ms_per_step": round(wall / steps * 1e3, 4), "finite": bool(e1[19] == 0)}
         rows.append(row)
         tot_int += b.interactions_per_eval() * 7 * steps
         tot_wall += wall
@@ -553,31 +714,22 @@ def main():
     tile_used = nbody.nbody_get_tile(sim.ctx, prec, autotune.size_class(int(np.diff(batch.offsets).max())))
     e_start = energy_fp64(sim) if args.workload in ("c1", "c2", "c3") else None
     nrows = min(int(batch.offsets[1]), ACCEL_ROWS)
-    accel_init = {prec: sim.accel().cpu().numpy()[:nrows].copy()}  # initial state, for the error table
     wall, kms, nlaunch = time_steps(sim, integrator, dt, args.steps, args.warmup, torch)
     e_end = energy_fp64(sim) if e_start is not None else None
     inter = inter_per_eval * evals_per_step * args.steps
     value = inter / wall / 1e9
     pair_ms = kms / max(nlaunch, 1)
-    achieved = FLOPS_PER_INTERACTION * inter_per_eval / (pair_ms * 1e-3) / 1e12
-    fam_peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
-    roofline = {
-        "bound": "alu",
-        "achieved": round(achieved, 3),
-        "peak": fam_peak,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / fam_peak, 4),
-        "traffic": traffic_from_profile(prec, tile_used, args.workload),
-        "busy_clock_ghz_profiled": (lambda f: float(f["busy_clock_ghz"]) if f and "busy_clock_ghz" in f else None)(
-            profile_summary(prec, tile_used, args.workload)),
+    roofline = pair_roofline(prec, inter_per_eval, pair_ms, tile_used, args.workload)
+    prof = profile_summary(prec, tile_used, args.workload)
+    roofline.update({
+        "busy_clock_ghz_profiled": float(prof["busy_clock_ghz"]) if prof and "busy_clock_ghz" in prof else None,
+        "issue_model": issue_model(prec, tile_used, args.workload),
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
                  "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
-        "kernel": "pair (%s)" % prec,
-        "kernel_ms": round(pair_ms, 4),
         "launches": nlaunch,
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "interactions_per_launch": inter_per_eval,
-    }
+    })
     a_gpu = sim.acc.cpu().numpy()
     pos_final = sim.pos.cpu().numpy()
     sim.close()
@@ -590,7 +742,6 @@ def main():
                 continue
             s2 = nbody.Simulation(batch, m)
             a0 = energy_fp64(s2)
-            accel_init[m] = s2.accel().cpu().numpy()[:nrows].copy()
             w2, k2, n2 = time_steps(s2, integrator, dt, args.steps, args.warmup, torch)
             modes[m] = {"G_interactions_per_s": round(inter_per_eval * evals_per_step * args.steps / w2 / 1e9, 2),
                         "pair_kernel_ms": round(k2 / max(n2, 1), 4),
@@ -624,39 +775,33 @@ def main():
         "roofline": roofline,
     }
     if e_start is not None:
+        # horizon: the warm-up plus the timed steps of this run (not the configuration's full count)
         result["energy"] = dict(drift_report(e_start, e_end), steps=args.steps + args.warmup,
                                 measured_in="fp64 library diagnostics")
     if modes:
         result["modes"] = modes
     if args.workload in ("c1", "c2"):
-        # the same run with step graphs on and off (wall clock, no per-kernel events)
-        gres = {}
-        for use in (True, False):
-            s3 = nbody.Simulation(batch, prec)
-            nbody.nbody_use_graphs(s3.ctx, use)
-            s3.accel()
-            s3.step(integrator, dt, args.steps)  # the same call as the timed one: graphs captured here
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s3.step(integrator, dt, args.steps)
-            torch.cuda.synchronize()
-            gres["graphs_on" if use else "graphs_off"] = round((time.perf_counter() - t0) / args.steps * 1e3, 4)
-            s3.close()
-        result["ms_per_step_graphs"] = gres
+        result["ms_per_step_graphs"] = graph_ab(batch, prec, integrator, dt, args.steps, torch)
     if args.workload == "c4":
         bsteps = max(1, min(args.steps, 3))
         el = per_cluster_baseline(batch, integrator, dt, bsteps, torch)
         per = inter_per_eval * evals_per_step * bsteps / el / 1e9
         result["per_cluster_launches"] = {"G_interactions_per_s": round(per, 3), "steps": bsteps,
                                           "batched_over_per_cluster": round(value / per, 2)}
+        result["accel_error"] = c4_accuracy(batch, torch)
     if not args.no_cpu_baseline:
         cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
         result["cpu_baseline"] = cb
         result["parity_sample"] = parity
-        result["accel_error_initial_state"] = mode_errors(batch, accel_init, nrows)
-        if args.workload in ("c2", "c3"):
-            result["accel_error_on_fp64_trajectory"] = sampled_state_errors(
-                batch, list(accel_init), integrator, dt, min(args.steps, 100), nrows, torch)
+    if not args.no_cpu_baseline and args.workload in ("c2", "c3"):
+        result["accel_error_on_fp64_trajectory"] = sampled_state_errors(
+            batch, [prec] + [m for m in modes], integrator, dt, [0, min(args.steps, 100) // 2, min(args.steps, 100)],
+            nrows, torch)
+    if args.workload == "c3" and not args.no_extras:
+        for key, fn in (("c1", lambda: extra_c1(torch)), ("c2", lambda: extra_c2(torch)),
+                        ("c4", lambda: extra_c4(torch)), ("c5", lambda: extra_c5(args))):
+            print("extras: %s" % key, file=sys.stderr, flush=True)
+            result[key] = fn()
     print(json.dumps(result), flush=True)
 
 

@@ -239,13 +239,13 @@ typedef struct {
 int nbody_set_tile(nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile tile);
 int nbody_get_tile(const nbody_ctx* ctx, int32_t prec, int32_t nclass, nbody_tile* tile);
 
-/* Step graphs (enable = 1; off by default, because replaying captured steps has measured slower
- * than launching the same kernels directly on gfx950 under ROCm 7).  When on, nbody_step_leapfrog /
+/* Step graphs (enable = 1, the default; 0 launches every kernel directly).  Replaying a captured
+ * step halves the gap between consecutive kernels on gfx950 under ROCm 7 (3.7 against 7.4 us in a
+ * kernel trace of the N = 1024 leapfrog), which is what bounds small systems.  When on, nbody_step_leapfrog /
  * nbody_step_sym6 calls with nsteps >= 2 capture the kernels of up to 8 steps into a HIP graph, and
  * nbody_substeps calls with nrounds >= 2 capture their rounds, once per argument set (a change of
  * any pointer, dt, system layout or launch shape recaptures; 8 graphs are cached), and replay them
- * on a context-owned stream ordered after, and before, the caller's stream.  Results are bitwise
- * those of the direct launches.  Disabled automatically while per-kernel timing is on. */
+ * on the caller's stream.  Results are bitwise those of the direct launches.  Disabled automatically while per-kernel timing is on. */
 int nbody_use_graphs(nbody_ctx* ctx, int enable);
 
 /* Per-kernel timing with HIP events recorded on the call's stream around every pair-kernel

@@ -128,6 +128,7 @@ struct StepGraph {
   std::vector<unsigned char> key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after its last replays; waited on before it is destroyed
 };
 
 struct nbody_ctx {
@@ -135,9 +136,8 @@ struct nbody_ctx {
   void* scratch = nullptr;  // device address of this device's copy of `scratch`
   Slot fixed;               // pinned staging of the no-allocation entry point, allocated at creation
   int cus = 256;
-  bool graphs = false;
-  hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are launched on
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool graphs = true;  // step graphs (nbody_use_graphs)
+  hipStream_t gstream = nullptr;  // non-blocking stream the step graphs are captured on
   std::vector<StepGraph> gcache;  // small LRU cache of captured graphs (most recent last)
   TileCfg tiles[kFamilies][kSizeClasses];
   Slot slots[4];
@@ -573,20 +573,26 @@ std::vector<unsigned char> graph_key(const Prepared& P, bool mask, int stages, F
   return key;
 }
 
+// Waits for a cached graph's last replays (on whatever stream they ran) and frees it.
+void destroy_graph(StepGraph& g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+  }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = StepGraph();
+}
+
 constexpr size_t kMaxGraphs = 8;
 constexpr int kGraphSteps = 8;
 
-// Launch `replays` replays of the graph of `stages` evaluations (captured once per argument set and
-// cached) on the context's stream, ordered after the caller's stream and before anything the
-// caller issues next on it.
+// Launch `replays` replays of the graph of `stages` evaluations (captured once per argument set on
+// the context's stream, and cached) on the caller's stream.
 template <class F>
 int replay_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t replays, hipStream_t s) {
   int rc;
-  if (!ctx->gstream) {
-    HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
-  }
+  if (!ctx->gstream) HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
   std::vector<unsigned char> key = graph_key(P, ctx->plan.anymask, stages, set_stage);
   auto& gs = ctx->gcache;
   size_t hit = gs.size();
@@ -606,11 +612,10 @@ int replay_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t 
     }
     HIP_TRY(hipStreamEndCapture(ctx->gstream, &g.graph));
     HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    HIP_TRY(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
     g.key = std::move(key);
     if (gs.size() == kMaxGraphs) {
-      (void)hipStreamSynchronize(ctx->gstream);
-      (void)hipGraphExecDestroy(gs.front().exec);
-      (void)hipGraphDestroy(gs.front().graph);
+      destroy_graph(gs.front());
       gs.erase(gs.begin());
     }
     gs.push_back(std::move(g));
@@ -621,12 +626,11 @@ int replay_graph(nbody_ctx* ctx, Prepared& P, int stages, F& set_stage, int32_t 
     gs.push_back(std::move(g));
     hit = gs.size() - 1;
   }
+  // replays go on the caller's stream itself (the context stream only records the capture), so they
+  // are ordered with the caller's work without cross-stream events
   hipGraphExec_t exec = gs[hit].exec;
-  HIP_TRY(hipEventRecord(ctx->ev_in, s));
-  HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
-  for (int32_t r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(exec, ctx->gstream));
-  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->gstream));
-  HIP_TRY(hipStreamWaitEvent(s, ctx->ev_out, 0));
+  for (int32_t r = 0; r < replays; ++r) HIP_TRY(hipGraphLaunch(exec, s));
+  HIP_TRY(hipEventRecord(gs[hit].done, s));
   return NB_OK;
 }
 
@@ -740,13 +744,7 @@ void nbody_destroy(nbody_ctx* ctx) {
     (void)hipEventDestroy(pr.second);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-  if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
-  for (StepGraph& g : ctx->gcache) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-  }
-  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
-  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  for (StepGraph& g : ctx->gcache) destroy_graph(g);
   if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
   delete ctx;
 }

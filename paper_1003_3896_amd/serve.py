@@ -127,6 +127,9 @@ class HipExecutor:
         self.G = G
         self.galaxy = tuple(galaxy) if galaxy is not None else nbody.System([0, 1], [0.0]).galaxy
         self.ctx = nbody.nbody_create(device)
+        # no step graphs: the batch layout changes at every job boundary, so most calls would
+        # capture a new graph instead of replaying one
+        nbody.nbody_use_graphs(self.ctx, False)
         # Results depend on the tile length and the waves per group (the fold pattern), not on the
         # i-particles per lane, blocks per CU or the phased loop: every size class gets the same
         # (tile, waves) and its own tuned rest, so a job's result does not depend on the batch.
