@@ -120,7 +120,8 @@ void nbody_destroy(nbody_ctx* ctx);
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
  * about 2^21/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
  * 512..2^20 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
- * per cluster for the sort of NB_FP32DL, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
+ * per cluster for the sort of NB_FP32DL, and for its per-item frames and far-tile bits 32 bytes per
+ * 64 particles and range plus N_b^2 / 2^16 bytes per cluster, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
  * its contents are the library's between calls (the caller must not modify it while calls using
  * it are in flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);

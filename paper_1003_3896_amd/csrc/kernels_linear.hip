@@ -10,57 +10,6 @@ namespace nb {
 
 enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3 };
 
-// Fixed-order reduction of V doubles per thread over the block (a shuffle tree inside each wave,
-// then the waves in order); result valid in thread 0.  sh needs [V][kBlock / 64].
-template <int V>
-__device__ __forceinline__ void block_reduce(double (&val)[V], double (*sh)[kBlock]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1)
-#pragma unroll
-    for (int q = 0; q < V; ++q) val[q] += __shfl_down(val[q], m);
-  __syncthreads();  // sh is free (a previous reduction has been read)
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < V; ++q) sh[q][wave] = val[q];
-  __syncthreads();
-  if (t == 0)
-#pragma unroll
-    for (int q = 0; q < V; ++q) {
-      double s = sh[q][0];
-      for (int w = 1; w < kBlock / 64; ++w) s += sh[q][w];
-      val[q] = s;
-    }
-}
-
-// Minima and maxima of V values per thread over the block; result valid in thread 0.
-template <int V>
-__device__ __forceinline__ void block_minmax(double (&mn)[V], double (&mx)[V], double (*sh)[kBlock]) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1)
-#pragma unroll
-    for (int q = 0; q < V; ++q) {
-      mn[q] = fmin(mn[q], __shfl_down(mn[q], m));
-      mx[q] = fmax(mx[q], __shfl_down(mx[q], m));
-    }
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < V; ++q) {
-      sh[q][wave] = mn[q];
-      sh[V + q][wave] = mx[q];
-    }
-  __syncthreads();
-  if (t == 0)
-#pragma unroll
-    for (int q = 0; q < V; ++q)
-      for (int w = 1; w < kBlock / 64; ++w) {
-        mn[q] = fmin(mn[q], sh[q][w]);
-        mx[q] = fmax(mx[q], sh[V + q][w]);
-      }
-}
-
 // Returns true in every thread of the block that finished cluster `cl` last (after its partial
 // was published by thread 0).
 __device__ __forceinline__ bool last_block_of_cluster(int* counter, int nchunks) {

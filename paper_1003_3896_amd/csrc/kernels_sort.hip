@@ -7,7 +7,7 @@
 // cluster's bounding box) in three passes of 10 bits.  Sort tiles never span clusters, so every
 // cluster is sorted on its own, and the result depends only on that cluster's positions: ties
 // keep the particles' own order, and no step depends on the timing of other blocks.
-#include "nb_internal.h"
+#include "nb_device.h"
 
 namespace nb {
 
@@ -179,6 +179,61 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args a) {
   a.spos[l] = make_double4(a.pos[3 * g], a.pos[3 * g + 1], a.pos[3 * g + 2], a.mass[g]);
 }
 
+// The local frame and the far-tile bits of one pair work item (one block per item), from the sorted
+// FP64 copy.  The frame is centred on the bounding box of the item's i-particles, ref = (lo + hi)/2,
+// with far2 = (3/4 of the box diagonal)^2 (with a 1e-6 relative margin); j-tile t of the item's
+// range is far when it is full and every one of its sources lies at |x_j - ref|^2 >= far2: then the
+// FP32 difference of two coordinates in that frame is within 1.5 x 2^-22 of the exact difference
+// (relative), and the pair kernel computes it without the double-single correction.  Each wave
+// decides 32 consecutive tiles at a time (its lanes split every tile's sources) and writes one word.
+__global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
+  __shared__ double sh[6][kBlock];
+  __shared__ double s_ref[4];
+  const PairItem item = a.items[blockIdx.x];
+  const DevCluster c = a.cl[item.cluster];
+  const int i1 = min(c.n, item.i0 + a.item_tile);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int l = item.i0 + (int)threadIdx.x; l < i1; l += kBlock) {
+    const double4 q = a.spos[c.off + l];
+    lo[0] = fmin(lo[0], q.x);
+    lo[1] = fmin(lo[1], q.y);
+    lo[2] = fmin(lo[2], q.z);
+    hi[0] = fmax(hi[0], q.x);
+    hi[1] = fmax(hi[1], q.y);
+    hi[2] = fmax(hi[2], q.z);
+  }
+  block_minmax<3>(lo, hi, sh);
+  if (threadIdx.x == 0) {
+    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    s_ref[0] = 0.5 * (lo[0] + hi[0]);
+    s_ref[1] = 0.5 * (lo[1] + hi[1]);
+    s_ref[2] = 0.5 * (lo[2] + hi[2]);
+    s_ref[3] = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
+    a.ibox[blockIdx.x] = make_double4(s_ref[0], s_ref[1], s_ref[2], s_ref[3]);
+  }
+  __syncthreads();
+  const double rx = s_ref[0], ry = s_ref[1], rz = s_ref[2], far2 = s_ref[3];
+  const int T = a.jtile;
+  const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
+  const int ntiles = (je - jb + T - 1) / T, nwords = (ntiles + 31) / 32;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = wave; q < nwords; q += kBlock / 64) {
+    unsigned word = 0;
+    for (int b = 0; b < 32 && 32 * q + b < ntiles; ++b) {
+      const int j0 = jb + (32 * q + b) * T;
+      if (j0 + T > je) continue;  // a partial tile is never far
+      bool ok = true;
+      for (int m = lane; m < T; m += 64) {
+        const double4 p = a.spos[c.off + j0 + m];
+        const double dx = p.x - rx, dy = p.y - ry, dz = p.z - rz;
+        ok = ok && dx * dx + dy * dy + dz * dz >= far2;
+      }
+      if (__ballot(!ok) == 0ull) word |= 1u << b;
+    }
+    if (lane == 0) a.farflags[item.flag0 + q] = word;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sort(const Args& a, int B, hipStream_t s) {
@@ -192,6 +247,7 @@ hipError_t launch_sort(const Args& a, int B, hipStream_t s) {
   }
   // three passes: the sorted order is in buffer 1
   hipLaunchKernelGGL(k_gather, dim3(a.nchunks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_farflags, dim3(a.nitems), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -49,9 +49,10 @@ struct Chunk {
 constexpr int kEnergySums = 17;
 constexpr int kEnergyOut = 20;
 
-// Pair work item: one i-tile of one cluster against one j-range (js) of it.
+// Pair work item: one i-tile of one cluster against one j-range (js) of it.  In the local mode
+// `flag0` is the item's first word of far-tile bits (bit t of the item's words: its j-tile t is far).
 struct PairItem {
-  int cluster, i0, js, pad;
+  int cluster, i0, js, flag0;
 };
 
 struct Galaxy {
@@ -80,6 +81,10 @@ struct Args {
   int* sbase;          // [B][kRadix] first destination of each digit in its cluster
   const int* perm;     // null: particles in their own order
   double4* spos;       // [Ntot] (x, y, z, m) in sorted order (NB_FP32DL), else null
+  double4* ibox;       // [items] centre of each item's i-particle box, w = (3/4 diagonal)^2 (NB_FP32DL)
+  unsigned* farflags;  // far-tile bits of every item (NB_FP32DL; item.flag0 is its first word)
+  int item_tile;       // i-particles of one work item (64 K (4/W))
+  int jtile;           // j-records of one LDS tile (T)
   double* mconst;      // [B] the common mass of a cluster whose masses are all equal, else 0
   double4* ref;        // [B] reference point of each cluster (centre of mass), w = total mass
   double4* part;       // partial sums (ax, ay, az, pot) of split clusters

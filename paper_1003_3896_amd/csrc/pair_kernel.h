@@ -24,7 +24,8 @@
 // FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction by 2^-24 |d|
 // more, at most 1.5 x 2^-22 |d| in all (R = D/2 <= 2 |d|, since |d| >= 3/4 D - R), so such a term
 // is as accurate as a double-single one up to a small factor; other tiles run the double-single
-// loop.
+// loop.  The sort pass computes every item's frame and one far bit per j-tile beforehand, so the
+// pair kernel decides a tile with one scalar load and stages only the high parts of a far tile.
 //
 // The results for a particle depend only on its own cluster's data and on (T, W) (in the local
 // family also on K, which sets the i-tile each coordinate frame is centred on): never on the other
@@ -155,6 +156,15 @@ __device__ __forceinline__ void store_tile(const Args& a, PairLds<FAM, T>& sh, c
         sh.lo[tid] = make_float4((float)(dx - (double)hx), (float)(dy - (double)hy), (float)(dz - (double)hz), 0.0f);
     }
   }
+}
+
+// Writes the fetched share of a full far tile of the local family: FP32 coordinates in the work
+// item's frame and the weight, the same values as store_tile's high parts (no low parts needed).
+template <int FAM, int T>
+__device__ __forceinline__ void store_far_tile(PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref, bool eq) {
+  const int tid = threadIdx.x;
+  if (tid >= T) return;
+  sh.hi[tid] = make_float4((float)(r.x - ref.x), (float)(r.y - ref.y), (float)(r.z - ref.z), eq ? 1.0f : (float)r.m);
 }
 
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
@@ -330,7 +340,6 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
   __shared__ PairLds<FAM, T> sh;
   __shared__ double red[W > 1 ? 4 * 64 * K * 4 : 1];
   __shared__ int s_item;
-  __shared__ double s_box[LOC ? 4 * 6 : 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / W, sub = wave % W;
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
@@ -338,8 +347,11 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     // with the extra scalar-register pressure)
     const PairItem item = LOC ? a.items[it] : load_item(a, it);
     const DevCluster c = LOC ? a.cl[item.cluster] : load_cluster(a, item.cluster);
-    double4 ref = a.ref[item.cluster];
-    if constexpr (!LOC) ref = make_double4(wave_uniform(ref.x), wave_uniform(ref.y), wave_uniform(ref.z), 0.0);
+    // the frame the coordinates are taken in: the cluster's centre of mass, or in the local family the
+    // centre of the item's i-particle box (computed with the item's far-tile bits by the sort pass)
+    const double4 r0 = LOC ? a.ibox[it] : a.ref[item.cluster];
+    const double4 ref = make_double4(wave_uniform(r0.x), wave_uniform(r0.y), wave_uniform(r0.z), 0.0);
+    const int flag0 = LOC ? wave_uniform(item.flag0) : 0;
     // != 0: every mass of the cluster equals mc
     const double mc = LOC ? a.mconst[item.cluster] : wave_uniform(a.mconst[item.cluster]);
     const bool eq = mc != 0.0;
@@ -353,41 +365,6 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     for (int k = 0; k < K; ++k) {
       li[k] = ibase + k * 64;
       gidx[k] = particle_index(a, c, li[k] < c.n ? li[k] : c.n - 1);
-    }
-    double far2 = INFINITY;  // LOC: a j-record at |x_j - ref|^2 >= far2 is far from every i-particle
-    if constexpr (LOC) {
-      // bounding box of the item's i-particles (FP64); ref = its centre, far2 = (3/4 diagonal)^2
-      double v[6];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        v[d] = v[3 + d] = a.pos[3 * gidx[0] + d];
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-          v[d] = fmin(v[d], a.pos[3 * gidx[k] + d]);
-          v[3 + d] = fmax(v[3 + d], a.pos[3 * gidx[k] + d]);
-        }
-      }
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          v[d] = fmin(v[d], __shfl_xor(v[d], m));
-          v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], m));
-        }
-      __syncthreads();  // s_box of the previous item has been read
-      if (lane == 0)
-#pragma unroll
-        for (int d = 0; d < 6; ++d) s_box[wave * 6 + d] = v[d];
-      __syncthreads();
-      double lo[3], hi[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = fmin(fmin(s_box[d], s_box[6 + d]), fmin(s_box[12 + d], s_box[18 + d]));
-        hi[d] = fmax(fmax(s_box[3 + d], s_box[9 + d]), fmax(s_box[15 + d], s_box[21 + d]));
-      }
-      ref = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]), 0.0);
-      const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
-      far2 = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -409,24 +386,24 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     const float e2 = c.eps2f;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
     TileRaw raw = fetch_tile<T>(a, c, jb, min(T, je - jb));
+    unsigned fw = 0;  // LOC: the far-tile bits of tiles [32 q, 32 q + 32) of this item
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
-      __syncthreads();
-      store_tile<FAM, T>(a, sh, raw, ref, eq);
       bool far = false;
       if constexpr (LOC) {
-        // a full tile is far when every record of it is (then the FP32 difference of the local
-        // coordinates is within 1.5 x 2^-22 relative of the exact one); decided for the whole block, so
-        // its waves take the same path and meet at the tile barriers together
-        bool ok = cnt == T;
-        if (ok && threadIdx.x < T) {
-          const double dx = raw.x - ref.x, dy = raw.y - ref.y, dz = raw.z - ref.z;
-          ok = dx * dx + dy * dy + dz * dz >= far2;
-        }
-        far = __syncthreads_and(ok);
-      } else {
-        __syncthreads();
+        // far tile: every source at least 3/4 of the item box diagonal from its centre, so the FP32
+        // difference of the local coordinates is within 1.5 x 2^-22 relative of the exact one
+        // (bits computed by the sort pass; the same for the whole block)
+        const int t = (j0 - jb) / T;
+        if ((t & 31) == 0) fw = a.farflags[flag0 + (t >> 5)];
+        far = (fw >> (t & 31)) & 1u;
       }
+      __syncthreads();
+      if (LOC && far)
+        store_far_tile<FAM, T>(sh, raw, ref, eq);
+      else
+        store_tile<FAM, T>(a, sh, raw, ref, eq);
+      __syncthreads();
       if (j0 + T < je) raw = fetch_tile<T>(a, c, j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
       if (LOC && far && eq)

@@ -74,7 +74,7 @@ void* g_scratch[kMaxDevices] = {};
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
   size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, eacc, part, skey, sval,
-      shist, sbase, spos, total;
+      shist, sbase, spos, ibox, flags, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -114,6 +114,9 @@ int split_of(int n) {
   while (s < 8 && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
   return s;
 }
+
+// 32-bit words holding one bit per j-tile of T records in a j-range of len sources.
+long long flag_words(int len, int T) { return ((long long)(len + T - 1) / T + 31) / 32; }
 
 int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : maxn < 131072 ? 2 : 3; }
 int family_of(int prec) {
@@ -205,7 +208,8 @@ int check_system(const nbody_system* sys) {
   return NB_OK;
 }
 
-Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart, int nstiles) {
+Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart, int nstiles,
+                   long long nflagwords) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
@@ -247,6 +251,10 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + (nstiles ? sizeof(int) * (size_t)B * kRadix : 0));
   L.spos = o;  // [ntot] sorted (x, y, z, m)
   o = align_up(o + (nstiles ? sizeof(double4) * (size_t)ntot : 0));
+  L.ibox = o;  // [items] centre of each work item's i-particle box, and (3/4 diagonal)^2 (NB_FP32DL)
+  o = align_up(o + (nstiles ? sizeof(double4) * (size_t)nitems_max : 0));
+  L.flags = o;  // far-tile bits of every work item's j-tiles (NB_FP32DL)
+  o = align_up(o + (nstiles ? sizeof(unsigned) * (size_t)nflagwords : 0));
   L.total = o;
   return L;
 }
@@ -263,7 +271,7 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.maxn = 0;
   p.anymask = false;
   p.anysplit = false;
-  long long nitems_max = 0, npart = 0;
+  long long nitems_max = 0, npart = 0, nflagwords = 0;
   for (int b = 0; b < p.B; ++b) {
     DevCluster& c = p.cl[b];
     c.off = sys->offsets[b];
@@ -287,6 +295,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
       p.anysplit = true;
     }
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
+    // far-tile words of those items: one bit per j-tile of the item's range (tiles of at least 128)
+    nflagwords += (long long)((c.n + 63) / 64) * c.split * flag_words(c.jlen, 128);
     c.stile0 = (int)p.stiles.size();
     c.nstiles = 0;
     if (sorted)
@@ -299,13 +309,13 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
   p.nstiles = (int)p.stiles.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart, p.nstiles);
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart, p.nstiles, nflagwords);
   return NB_OK;
 }
 
 // Pair work items for i-tiles of 64 K (4 / W) particles (item_tile), longest j-ranges first (ties
 // by cluster index).
-void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
+void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items, bool flags) {
   std::vector<int> order(p.B);
   for (int b = 0; b < p.B; ++b) order[b] = b;
   // longest items first: the cost of an item is its j-range length
@@ -313,9 +323,17 @@ void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items) {
   items.clear();
   const int tile = item_tile(t);
   // j-range major: the blocks running at the same time stream the same sources through L2
+  // in the local mode `pad` is the item's first word of far-tile bits
+  int words = 0;
   for (int b : order)
-    for (int js = 0; js < p.cl[b].split; ++js)
-      for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) items.push_back(PairItem{b, i0, js, 0});
+    for (int js = 0; js < p.cl[b].split; ++js) {
+      const int len = std::min(p.cl[b].n - js * p.cl[b].jlen, p.cl[b].jlen);
+      const int w = flags ? (int)flag_words(len, t.tile) : 0;
+      for (int i0 = 0; i0 < p.cl[b].n; i0 += tile) {
+        items.push_back(PairItem{b, i0, js, words});
+        words += w;
+      }
+    }
 }
 
 Slot* get_slot(nbody_ctx* ctx, size_t bytes, int* rc) {
@@ -382,7 +400,7 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   const int fam = family_of(sys->prec);
   const TileCfg t = ctx->tiles[fam][size_class(p.maxn)];
   std::vector<PairItem> items;
-  make_items(p, t, items);
+  make_items(p, t, items, p.nstiles > 0);
   // host blob: [clusters | chunks | items | counters | coefficients of the used rounds]
   const Layout& L = p.L;
   const size_t coef_bytes = coef3 ? sizeof(double) * 3 * (size_t)p.B * rounds : 0;
@@ -424,6 +442,10 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.sbase = reinterpret_cast<int*>(w + L.sbase);
   a.perm = p.nstiles ? a.sval[1] : nullptr;
   a.spos = p.nstiles ? reinterpret_cast<double4*>(w + L.spos) : nullptr;
+  a.ibox = p.nstiles ? reinterpret_cast<double4*>(w + L.ibox) : nullptr;
+  a.farflags = p.nstiles ? reinterpret_cast<unsigned*>(w + L.flags) : nullptr;
+  a.item_tile = item_tile(t);
+  a.jtile = t.tile;
   a.mconst = reinterpret_cast<double*>(w + L.mconst);
   a.ref = reinterpret_cast<double4*>(w + L.ref);
   a.epart = reinterpret_cast<double*>(w + L.epart);
@@ -478,7 +500,7 @@ int evaluate(nbody_ctx* ctx, Prepared& P, bool update, bool potmode, bool kick, 
   e = launch_update(P.a, ctx->plan.B, update, s);  // also clears the pair kernel's work counter
   if (e != hipSuccess) return fail(NB_ERR_HIP, "update kernel launch: %s", hipGetErrorString(e));
   if (P.a.nstiles) {
-    e = launch_sort(P.a, ctx->plan.B, s);
+    e = launch_sort(P.a, ctx->plan.B, s);  // also the work items' boxes and far-tile bits
     if (e != hipSuccess) return fail(NB_ERR_HIP, "sort kernel launch: %s", hipGetErrorString(e));
   }
   int rc = pair(ctx, P, potmode, kick, s);
@@ -768,7 +790,10 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   const long long nitems = 8 * (B + n / 64);
   const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
   const long long nstiles = B + n / kSortTile;  // the sort of NB_FP32DL
-  return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles).total;
+  // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/4096)
+  // <= (n/64 + B) (8 + (n + 8)/4096), since split_c <= 8 and split_c jlen_c <= n_c + split_c
+  const long long nflagwords = (n / 64 + B) * (8 + (n + 8) / 4096 + 1);
+  return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles, nflagwords).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {
