@@ -58,7 +58,9 @@ def parse():
     ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="c3: skip the c1/c2/c4/c5 keys")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the c1/c2/c4/c5 keys of the c3 run, the graph A/B of c1/c2 and the per-cluster "
+                         "baseline of c4 (profiling runs)")
     ap.add_argument("--extra-jobs", type=int, default=120, help="c3 extras: jobs of the bounded C5 stream")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -152,6 +154,18 @@ def issue_model(prec, tile=None, workload="c3"):
             "ceiling_frac_trans_paired": round(20.0 / cyc[1], 4),
             "model": "20 cycles per wave-interaction at peak; VALU %.2f cycles, transcendental %g (unpaired) or "
                      "%g (paired); packed FP32 not used" % (ISSUE_VALU_CYCLES, *ISSUE_TRANS_CYCLES)}
+
+
+def loop_probe(k, torch):
+    """The pair kernel's FP32 far-tile loop alone on this GPU (nbody_loop_probe): SIMD cycles per
+    wave-interaction, and the ceiling 20 / cycles it sets on the fraction of the FP32 peak."""
+    from paper_1003_3896_amd import nbody
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    buf = torch.empty(6 * 256 * cus, dtype=torch.float32, device="cuda")
+    cyc = min(nbody.nbody_loop_probe(0, buf, buf.numel() * 4, k) for _ in range(3))
+    return {"k": k, "cycles_per_wave_interaction": round(cyc, 3), "ceiling_frac": round(20.0 / cyc, 4),
+            "what": "the far-tile pair term (11 VALU + v_rsq_f32) over one LDS tile at 6 waves per SIMD, "
+                    "nothing else in the loop; SIMD cycles at the nominal 2.4 GHz"}
 
 
 def time_steps(sim, integrator, dt, steps, warmup, torch):
@@ -724,12 +738,15 @@ def main():
     roofline.update({
         "busy_clock_ghz_profiled": float(prof["busy_clock_ghz"]) if prof and "busy_clock_ghz" in prof else None,
         "issue_model": issue_model(prec, tile_used, args.workload),
+        "pair_loop_probe": loop_probe(tile_used[0], torch) if prec != "fp64" else None,
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
                  "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
         "launches": nlaunch,
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "interactions_per_launch": inter_per_eval,
     })
+    if roofline["pair_loop_probe"]:
+        roofline["frac_of_loop_ceiling"] = round(roofline["frac"] / roofline["pair_loop_probe"]["ceiling_frac"], 4)
     a_gpu = sim.acc.cpu().numpy()
     pos_final = sim.pos.cpu().numpy()
     sim.close()
@@ -780,9 +797,9 @@ def main():
                                 measured_in="fp64 library diagnostics")
     if modes:
         result["modes"] = modes
-    if args.workload in ("c1", "c2"):
+    if args.workload in ("c1", "c2") and not args.no_extras:
         result["ms_per_step_graphs"] = graph_ab(batch, prec, integrator, dt, args.steps, torch)
-    if args.workload == "c4":
+    if args.workload == "c4" and not args.no_extras:
         bsteps = max(1, min(args.steps, 3))
         el = per_cluster_baseline(batch, integrator, dt, bsteps, torch)
         per = inter_per_eval * evals_per_step * bsteps / el / 1e9

@@ -4,7 +4,7 @@
 namespace nb {
 
 bool tile_supported(int family, const TileCfg& t) {
-  const bool kw = (t.k == 1 && (t.w == 4 || (family != FAM_DL && (t.w == 1 || t.w == 2)))) ||
+  const bool kw = (t.k == 1 && (t.w == 4 || t.w == 2 || (family != FAM_DL && t.w == 1))) ||
                   (t.k == 2 && (t.w == 2 || t.w == 4));
   const bool ph = t.phase == 0 || ((family == FAM_F32 || family == FAM_DS) &&
                                    ((t.k == 1 && t.w == 4 && t.tile == 256) ||

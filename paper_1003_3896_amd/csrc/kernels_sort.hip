@@ -179,54 +179,111 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args a) {
   a.spos[l] = make_double4(a.pos[3 * g], a.pos[3 * g + 1], a.pos[3 * g + 2], a.mass[g]);
 }
 
-// The local frame and the far-tile bits of one pair work item (one block per item), from the sorted
+// Bounding boxes of the j-tiles of every range of every cluster (the tiles of T sorted sources the
+// pair kernel stages, from the start of each range), for the far-tile test below.  One wave per box
+// slot: cluster c owns slots [tbox0, tbox0 + split ceil(jlen/128)) and uses the first
+// split ceil(jlen/T) of them (range js, tile t at js ceil(jlen/T) + t); the lanes split the sources.
+__global__ __launch_bounds__(kBlock) void k_tileboxes(Args a, int B, int nslots) {
+  const int slot = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (slot >= nslots) return;
+  int lo = 0, hi = B - 1;  // the last cluster whose first slot is <= slot
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.cl[mid].tbox0 <= slot) lo = mid;
+    else hi = mid - 1;
+  }
+  const DevCluster c = a.cl[lo];
+  const int T = a.jtile;
+  const int per = (c.jlen + T - 1) / T;  // tiles of a full range
+  const int local = slot - c.tbox0, js = local / per, t = local % per;
+  if (js >= c.split) return;
+  const int jb = js * c.jlen, je = min(c.n, jb + c.jlen), j0 = jb + t * T;
+  if (j0 >= je) return;
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int m = lane; m < T && j0 + m < je; m += 64) {
+    const double4 p = a.spos[c.off + j0 + m];
+    v[0] = fmin(v[0], p.x);
+    v[1] = fmin(v[1], p.y);
+    v[2] = fmin(v[2], p.z);
+    v[3] = fmax(v[3], p.x);
+    v[4] = fmax(v[4], p.y);
+    v[5] = fmax(v[5], p.z);
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v[d] = fmin(v[d], __shfl_xor(v[d], s));
+      v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], s));
+    }
+  double* out = a.tbox + 6 * (size_t)slot;
+#pragma unroll
+  for (int d = 0; d < 6; ++d)
+    if (lane == d) out[d] = v[d];
+}
+
+// The local frame and the far-tile bits of the pair work items (one wave per item), from the sorted
 // FP64 copy.  The frame is centred on the bounding box of the item's i-particles, ref = (lo + hi)/2,
 // with far2 = (3/4 of the box diagonal)^2 (with a 1e-6 relative margin); j-tile t of the item's
 // range is far when it is full and every one of its sources lies at |x_j - ref|^2 >= far2: then the
 // FP32 difference of two coordinates in that frame is within 1.5 x 2^-22 of the exact difference
-// (relative), and the pair kernel computes it without the double-single correction.  Each wave
-// decides 32 consecutive tiles at a time (its lanes split every tile's sources) and writes one word.
+// (relative), and the pair kernel computes it without the double-single correction.  A tile whose
+// bounding box already lies that far (one lane per tile) is far; only the others are tested source
+// by source (the lanes split the tile's sources).  32 consecutive tiles make one word.
 __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
-  __shared__ double sh[6][kBlock];
-  __shared__ double s_ref[4];
-  const PairItem item = a.items[blockIdx.x];
+  const int it = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (it >= a.nitems) return;
+  const PairItem item = a.items[it];
   const DevCluster c = a.cl[item.cluster];
   const int i1 = min(c.n, item.i0 + a.item_tile);
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int l = item.i0 + (int)threadIdx.x; l < i1; l += kBlock) {
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int l = item.i0 + lane; l < i1; l += 64) {
     const double4 q = a.spos[c.off + l];
-    lo[0] = fmin(lo[0], q.x);
-    lo[1] = fmin(lo[1], q.y);
-    lo[2] = fmin(lo[2], q.z);
-    hi[0] = fmax(hi[0], q.x);
-    hi[1] = fmax(hi[1], q.y);
-    hi[2] = fmax(hi[2], q.z);
+    v[0] = fmin(v[0], q.x);
+    v[1] = fmin(v[1], q.y);
+    v[2] = fmin(v[2], q.z);
+    v[3] = fmax(v[3], q.x);
+    v[4] = fmax(v[4], q.y);
+    v[5] = fmax(v[5], q.z);
   }
-  block_minmax<3>(lo, hi, sh);
-  if (threadIdx.x == 0) {
-    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
-    s_ref[0] = 0.5 * (lo[0] + hi[0]);
-    s_ref[1] = 0.5 * (lo[1] + hi[1]);
-    s_ref[2] = 0.5 * (lo[2] + hi[2]);
-    s_ref[3] = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
-    a.ibox[blockIdx.x] = make_double4(s_ref[0], s_ref[1], s_ref[2], s_ref[3]);
-  }
-  __syncthreads();
-  const double rx = s_ref[0], ry = s_ref[1], rz = s_ref[2], far2 = s_ref[3];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v[d] = fmin(v[d], __shfl_xor(v[d], s));
+      v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], s));
+    }
+  const double dx = v[3] - v[0], dy = v[4] - v[1], dz = v[5] - v[2];
+  const double rx = 0.5 * (v[0] + v[3]), ry = 0.5 * (v[1] + v[4]), rz = 0.5 * (v[2] + v[5]);
+  const double far2 = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
+  if (lane == 0) a.ibox[it] = make_double4(rx, ry, rz, far2);
   const int T = a.jtile;
   const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
   const int ntiles = (je - jb + T - 1) / T, nwords = (ntiles + 31) / 32;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int q = wave; q < nwords; q += kBlock / 64) {
-    unsigned word = 0;
-    for (int b = 0; b < 32 && 32 * q + b < ntiles; ++b) {
+  const double* tb = a.tbox + 6 * ((size_t)c.tbox0 + (size_t)item.js * ((c.jlen + T - 1) / T));
+  for (int q = 0; q < nwords; ++q) {
+    // box test: lane b < 32 takes tile 32 q + b
+    const int tl = 32 * q + lane;
+    bool boxfar = false, full = false;
+    if (lane < 32 && tl < ntiles) {
+      full = jb + (tl + 1) * T <= je;  // a partial tile is never far
+      const double* b = tb + 6 * (size_t)tl;
+      const double gx = fmax(0.0, fmax(b[0] - rx, rx - b[3]));
+      const double gy = fmax(0.0, fmax(b[1] - ry, ry - b[4]));
+      const double gz = fmax(0.0, fmax(b[2] - rz, rz - b[5]));
+      boxfar = full && gx * gx + gy * gy + gz * gz >= far2;
+    }
+    unsigned word = (unsigned)__ballot(boxfar);
+    unsigned todo = (unsigned)__ballot(full && !boxfar);
+    while (todo) {  // full tiles the box test left open: source by source
+      const int b = __ffs(todo) - 1;
+      todo &= todo - 1;
       const int j0 = jb + (32 * q + b) * T;
-      if (j0 + T > je) continue;  // a partial tile is never far
       bool ok = true;
       for (int m = lane; m < T; m += 64) {
         const double4 p = a.spos[c.off + j0 + m];
-        const double dx = p.x - rx, dy = p.y - ry, dz = p.z - rz;
-        ok = ok && dx * dx + dy * dy + dz * dz >= far2;
+        const double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
+        ok = ok && ex * ex + ey * ey + ez * ez >= far2;
       }
       if (__ballot(!ok) == 0ull) word |= 1u << b;
     }
@@ -247,7 +304,9 @@ hipError_t launch_sort(const Args& a, int B, hipStream_t s) {
   }
   // three passes: the sorted order is in buffer 1
   hipLaunchKernelGGL(k_gather, dim3(a.nchunks), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_farflags, dim3(a.nitems), dim3(kBlock), 0, s, a);
+  const int waves = kBlock / 64;
+  hipLaunchKernelGGL(k_tileboxes, dim3((a.ntboxes + waves - 1) / waves), dim3(kBlock), 0, s, a, B, a.ntboxes);
+  hipLaunchKernelGGL(k_farflags, dim3((a.nitems + waves - 1) / waves), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

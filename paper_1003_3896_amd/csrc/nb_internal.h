@@ -35,6 +35,8 @@ struct DevCluster {
   int jlen;            // sources per range (the last range may be shorter)
   int stile0;          // first sort tile of the cluster (NB_FP32DL)
   int nstiles;         // sort tiles of the cluster
+  int tbox0;           // first j-tile box of the cluster (NB_FP32DL; room for split x ceil(jlen/128))
+  int pad0;
 };
 constexpr int kFlagField = 1;     // add the galaxy field
 constexpr int kFlagMaskSelf = 2;  // eps == 0: the j = i term must be excluded explicitly
@@ -82,6 +84,8 @@ struct Args {
   const int* perm;     // null: particles in their own order
   double4* spos;       // [Ntot] (x, y, z, m) in sorted order (NB_FP32DL), else null
   double4* ibox;       // [items] centre of each item's i-particle box, w = (3/4 diagonal)^2 (NB_FP32DL)
+  double* tbox;        // [ntboxes][6] bounding box (min xyz, max xyz) of every j-tile (NB_FP32DL)
+  int ntboxes;         // box slots (NB_FP32DL)
   unsigned* farflags;  // far-tile bits of every item (NB_FP32DL; item.flag0 is its first word)
   int item_tile;       // i-particles of one work item (64 K (4/W))
   int jtile;           // j-records of one LDS tile (T)

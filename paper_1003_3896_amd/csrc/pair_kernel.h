@@ -596,8 +596,8 @@ PairFn pair_flags(bool fold, bool mask, bool pot) {
   }
 }
 
-// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)} ((1,4), (2,2), (2,4) for the
-// local family), T in {128, 256}; the rsq-phased full-tile loop for the FP32 and double-single
+// Compiled-in shapes: (K, W) in {(1,1), (1,2), (1,4), (2,2), (2,4)} (all but (1,1) for the local
+// family), T in {128, 256}; the rsq-phased full-tile loop for the FP32 and double-single
 // families' main shapes, used for folded sums without the self mask or the potential.
 template <int FAM>
 PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
@@ -617,9 +617,9 @@ PairFn pair_select(const TileCfg& t, bool fold, bool mask, bool pot) {
   if constexpr (FAM != FAM_DL) {
     NB_SHAPE(1, 1, 128)
     NB_SHAPE(1, 1, 256)
-    NB_SHAPE(1, 2, 128)
-    NB_SHAPE(1, 2, 256)
   }
+  NB_SHAPE(1, 2, 128)
+  NB_SHAPE(1, 2, 256)
   NB_SHAPE(1, 4, 128)
   NB_SHAPE(1, 4, 256)
   NB_SHAPE(2, 2, 128)

@@ -74,7 +74,7 @@ void* g_scratch[kMaxDevices] = {};
 // Workspace layout of one system (depends on the system only, not on the tile choice).
 struct Layout {
   size_t cl, chunks, stiles, items, counters, coef, ref, mconst, box, partials, epart, pot, eacc, part, skey, sval,
-      shist, sbase, spos, ibox, flags, total;
+      shist, sbase, spos, ibox, tbox, flags, total;
   size_t blob;  // bytes of the uploaded prefix [cl .. counters] (the coefficients follow it)
 };
 
@@ -83,6 +83,7 @@ struct Plan {
   long long ntot = 0;
   int nchunks = 0;
   int nstiles = 0;  // sort tiles (NB_FP32DL only)
+  int ntboxes = 0;  // j-tile box slots (NB_FP32DL only)
   int maxn = 0;
   bool anymask = false;
   bool anysplit = false;
@@ -209,7 +210,7 @@ int check_system(const nbody_system* sys) {
 }
 
 Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, long long npart, int nstiles,
-                   long long nflagwords) {
+                   long long nflagwords, long long ntiles) {
   Layout L{};
   size_t o = 0;
   L.cl = o;
@@ -253,6 +254,8 @@ Layout make_layout(int B, long long ntot, int nchunks, long long nitems_max, lon
   o = align_up(o + (nstiles ? sizeof(double4) * (size_t)ntot : 0));
   L.ibox = o;  // [items] centre of each work item's i-particle box, and (3/4 diagonal)^2 (NB_FP32DL)
   o = align_up(o + (nstiles ? sizeof(double4) * (size_t)nitems_max : 0));
+  L.tbox = o;  // [tiles][6] bounding box of every j-tile (NB_FP32DL)
+  o = align_up(o + (nstiles ? sizeof(double) * 6 * (size_t)ntiles : 0));
   L.flags = o;  // far-tile bits of every work item's j-tiles (NB_FP32DL)
   o = align_up(o + (nstiles ? sizeof(unsigned) * (size_t)nflagwords : 0));
   L.total = o;
@@ -271,7 +274,7 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.maxn = 0;
   p.anymask = false;
   p.anysplit = false;
-  long long nitems_max = 0, npart = 0, nflagwords = 0;
+  long long nitems_max = 0, npart = 0, nflagwords = 0, ntiles = 0;
   for (int b = 0; b < p.B; ++b) {
     DevCluster& c = p.cl[b];
     c.off = sys->offsets[b];
@@ -297,6 +300,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
     // far-tile words of those items: one bit per j-tile of the item's range (tiles of at least 128)
     nflagwords += (long long)((c.n + 63) / 64) * c.split * flag_words(c.jlen, 128);
+    c.tbox0 = (int)ntiles;  // the cluster's j-tile boxes: room for split ranges of tiles of >= 128
+    ntiles += (long long)c.split * ((c.jlen + 127) / 128);
     c.stile0 = (int)p.stiles.size();
     c.nstiles = 0;
     if (sorted)
@@ -309,7 +314,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
   p.ntot = sys->offsets[p.B];
   p.nchunks = (int)p.chunks.size();
   p.nstiles = (int)p.stiles.size();
-  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart, p.nstiles, nflagwords);
+  p.ntboxes = (int)ntiles;
+  p.L = make_layout(p.B, p.ntot, p.nchunks, nitems_max, npart, p.nstiles, nflagwords, ntiles);
   return NB_OK;
 }
 
@@ -443,6 +449,8 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.perm = p.nstiles ? a.sval[1] : nullptr;
   a.spos = p.nstiles ? reinterpret_cast<double4*>(w + L.spos) : nullptr;
   a.ibox = p.nstiles ? reinterpret_cast<double4*>(w + L.ibox) : nullptr;
+  a.tbox = p.nstiles ? reinterpret_cast<double*>(w + L.tbox) : nullptr;
+  a.ntboxes = p.nstiles ? p.ntboxes : 0;
   a.farflags = p.nstiles ? reinterpret_cast<unsigned*>(w + L.flags) : nullptr;
   a.item_tile = item_tile(t);
   a.jtile = t.tile;
@@ -793,7 +801,9 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/4096)
   // <= (n/64 + B) (8 + (n + 8)/4096), since split_c <= 8 and split_c jlen_c <= n_c + split_c
   const long long nflagwords = (n / 64 + B) * (8 + (n + 8) / 4096 + 1);
-  return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles, nflagwords).total;
+  // j-tile boxes: sum over clusters of split_c ceil(jlen_c/128) <= n/128 + 9 B
+  const long long ntiles = n / 128 + 9 * B;
+  return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles, nflagwords, ntiles).total;
 }
 
 int64_t nbody_interactions(const nbody_system* sys) {
