@@ -87,11 +87,7 @@ ACCEL_ROWS = 2048  # rows of the per-mode accuracy table
 
 
 PROFILE_TAG = {"c3": "plummer262144", "c2": "salpeter65536", "c4": "ensemble512"}  # committed counter summaries
-# issue model of the FP32 pair loop on gfx950 (measured, without packed FP32): an FP32 VALU
-# instruction every 2.45 SIMD cycles with dual issue across waves, a transcendental 16 cycles inside a
-# VALU stream (8 when two waves' transcendentals pair); a wave-interaction is 20 cycles at peak
-ISSUE_VALU_CYCLES = 2.45
-ISSUE_TRANS_CYCLES = (16.0, 8.0)
+
 # sources that decide what a pair-kernel launch does (its code, work items and split rule)
 PAIR_SOURCES = [os.path.join(ROOT, "paper_1003_3896_amd", "csrc", f)
                 for f in ("pair_kernel.h", "nb_device.h", "nb_internal.h", "runtime.hip")]
@@ -140,32 +136,17 @@ def traffic_from_profile(prec, tile=None, workload="c3"):
         return None
 
 
-def issue_model(prec, tile=None, workload="c3"):
-    """The issue-model ceiling of the pair kernel from the committed counter summary (VALU and
-    transcendental instructions per wave-interaction), or None."""
+def issue_counters(prec, tile=None, workload="c3"):
+    """The pair kernel's instruction mix and cycles per wave-interaction (20 at the FP32 vector peak)
+    from the committed counter summary, or None."""
     f = profile_summary(prec, tile, workload)
     try:
-        valu, trans = float(f["valu_per_wave_interaction"]), float(f["trans_per_wave_interaction"])
+        return {"valu_per_wave_interaction": float(f["valu_per_wave_interaction"]),
+                "trans_per_wave_interaction": float(f["trans_per_wave_interaction"]),
+                "busy_clock_ghz": float(f["busy_clock_ghz"]),
+                "source": "rocprofv3 counters of the committed summary (another run of the same kernel)"}
     except (TypeError, KeyError, ValueError):
         return None
-    cyc = [valu * ISSUE_VALU_CYCLES + trans * t for t in ISSUE_TRANS_CYCLES]
-    return {"valu_per_wave_interaction": valu, "trans_per_wave_interaction": trans,
-            "ceiling_frac_trans_unpaired": round(20.0 / cyc[0], 4),
-            "ceiling_frac_trans_paired": round(20.0 / cyc[1], 4),
-            "model": "20 cycles per wave-interaction at peak; VALU %.2f cycles, transcendental %g (unpaired) or "
-                     "%g (paired); packed FP32 not used" % (ISSUE_VALU_CYCLES, *ISSUE_TRANS_CYCLES)}
-
-
-def loop_probe(k, torch):
-    """The pair kernel's FP32 far-tile loop alone on this GPU (nbody_loop_probe): SIMD cycles per
-    wave-interaction, and the ceiling 20 / cycles it sets on the fraction of the FP32 peak."""
-    from paper_1003_3896_amd import nbody
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    buf = torch.empty(6 * 256 * cus, dtype=torch.float32, device="cuda")
-    cyc = min(nbody.nbody_loop_probe(0, buf, buf.numel() * 4, k) for _ in range(3))
-    return {"k": k, "cycles_per_wave_interaction": round(cyc, 3), "ceiling_frac": round(20.0 / cyc, 4),
-            "what": "the far-tile pair term (11 VALU + v_rsq_f32) over one LDS tile at 6 waves per SIMD, "
-                    "nothing else in the loop; SIMD cycles at the nominal 2.4 GHz"}
 
 
 def time_steps(sim, integrator, dt, steps, warmup, torch):
@@ -737,16 +718,13 @@ def main():
     prof = profile_summary(prec, tile_used, args.workload)
     roofline.update({
         "busy_clock_ghz_profiled": float(prof["busy_clock_ghz"]) if prof and "busy_clock_ghz" in prof else None,
-        "issue_model": issue_model(prec, tile_used, args.workload),
-        "pair_loop_probe": loop_probe(tile_used[0], torch) if prec != "fp64" else None,
+        "issue_counters": issue_counters(prec, tile_used, args.workload),
         "tile": {"k": tile_used[0], "waves_per_group": tile_used[1], "tile": tile_used[2],
                  "blocks_per_cu": tile_used[3], "phased": tile_used[4]},
         "launches": nlaunch,
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "interactions_per_launch": inter_per_eval,
     })
-    if roofline["pair_loop_probe"]:
-        roofline["frac_of_loop_ceiling"] = round(roofline["frac"] / roofline["pair_loop_probe"]["ceiling_frac"], 4)
     a_gpu = sim.acc.cpu().numpy()
     pos_final = sim.pos.cpu().numpy()
     sim.close()

@@ -256,14 +256,6 @@ int nbody_use_graphs(nbody_ctx* ctx, int enable);
 int nbody_timing_enable(nbody_ctx* ctx, int enable);
 int nbody_timing_read(nbody_ctx* ctx, double* ms_total, int64_t* launches);
 
-/* Issue rate of the pair kernel's FP32 inner loop on device `device`: runs the far-tile pair term
- * (k = 1 or 2 i-particles per lane) over one LDS tile, repeatedly, at 6 waves per SIMD with nothing
- * else in the loop, and returns in *cycles the SIMD cycles per wave-interaction at the nominal
- * 2.4 GHz (20 at the FP32 vector peak).  buf: a device buffer of at least 6 x 256 x (compute units)
- * floats, overwritten.  Synchronous (waits for its kernels on the null stream).  NB_ERR_ARG for bad
- * arguments, NB_ERR_HIP on a HIP failure. */
-int nbody_loop_probe(int device, void* buf, size_t buf_bytes, int k, double* cycles);
-
 /* Pair interactions one force evaluation of `sys` performs: sum_b N_b^2 (j = i counted). */
 int64_t nbody_interactions(const nbody_system* sys);
 

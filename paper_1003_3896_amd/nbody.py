@@ -27,7 +27,6 @@ EXPORTS = (
     "nbody_step_leapfrog", "nbody_step_sym6", "nbody_energy", "nbody_last_error", "nbody_set_tile",
     "nbody_get_tile", "nbody_timing_enable", "nbody_timing_read", "nbody_interactions", "nbody_use_graphs",
     "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max", "nbody_accel_noalloc",
-    "nbody_loop_probe",
 )
 # limits of nbody_accel_noalloc (NB_NOALLOC_SCRATCH_BYTES, NB_NOALLOC_TABLE_BYTES in include/nbody.h)
 NOALLOC_SCRATCH_BYTES = 128 << 20
@@ -103,8 +102,6 @@ def lib():
         L.nbody_use_graphs.argtypes = [P, ctypes.c_int]
         L.nbody_sym6_coefficients.argtypes = [P, P]
         L.nbody_timing_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
-        L.nbody_loop_probe.argtypes = [ctypes.c_int, P, SZ, ctypes.c_int, ctypes.POINTER(D)]
-        L.nbody_loop_probe.restype = ctypes.c_int
         L.nbody_interactions.argtypes = [SYS]
         L.nbody_interactions.restype = I64
         for name in ("nbody_create", "nbody_accel", "nbody_accel_noalloc", "nbody_substep", "nbody_step_leapfrog", "nbody_step_sym6",
@@ -301,15 +298,6 @@ def nbody_timing_read(ctx):
     n = ctypes.c_int64()
     _check(lib().nbody_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
-
-
-def nbody_loop_probe(device: int, buf, buf_bytes: int, k: int) -> float:
-    """SIMD cycles per wave-interaction of the FP32 pair loop alone (20 at the FP32 vector peak)."""
-    c = ctypes.c_double()
-    rc = lib().nbody_loop_probe(int(device), _addr(buf), int(buf_bytes), int(k), ctypes.byref(c))
-    if rc != NB_OK:
-        raise NBodyError(rc, "nbody_loop_probe failed")
-    return c.value
 
 
 def nbody_last_error() -> str:
