@@ -332,6 +332,25 @@ def sampled_state_errors(batch, modes, integrator, dt, targets, nrows, torch):
     return out
 
 
+def all_particle_errors(batch, pos, modes, torch):
+    """Every mode's force evaluation at positions pos against the library's FP64 evaluation of the
+    same state, over ALL particles (the FP64 mode matches the oracle to 1e-15 in the tests): the
+    a_rms, per-particle and L2 metrics of paper_1003_3896_amd.accuracy (no S_i: that needs the
+    oracle)."""
+    from paper_1003_3896_amd import accuracy, nbody
+    ref = nbody.Simulation(batch, "fp64")
+    ref.pos.copy_(torch.as_tensor(pos, dtype=torch.float64, device="cuda"))
+    a64 = ref.accel().cpu().numpy()
+    out = {}
+    for m in modes:
+        sm = nbody.Simulation(batch, m)
+        sm.pos.copy_(ref.pos)
+        out[m] = accuracy.short(accuracy.accel_error(sm.accel().cpu().numpy(), a64, offsets=batch.offsets))
+        sm.close()
+    ref.close()
+    return out
+
+
 def graph_ab(batch, prec, integrator, dt, steps, torch):
     """Wall-clock ms per step of the same run with step graphs on and off (no per-kernel events)."""
     from paper_1003_3896_amd import nbody
@@ -788,6 +807,10 @@ def main():
         cb, parity = cpu_baseline(batch, pos_final, args.cpu_seconds, a_gpu)
         result["cpu_baseline"] = cb
         result["parity_sample"] = parity
+    if args.workload in ("c2", "c3", "c4"):
+        result["accel_error_all_particles_vs_fp64"] = dict(
+            all_particle_errors(batch, pos_final, [prec] + [m for m in modes if m != "fp64"], torch),
+            state="the final state of the timed run")
     if not args.no_cpu_baseline and args.workload in ("c2", "c3"):
         result["accel_error_on_fp64_trajectory"] = sampled_state_errors(
             batch, [prec] + [m for m in modes], integrator, dt, [0, min(args.steps, 100) // 2, min(args.steps, 100)],
