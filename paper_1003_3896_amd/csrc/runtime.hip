@@ -329,7 +329,7 @@ void make_items(const Plan& p, const TileCfg& t, std::vector<PairItem>& items, b
   items.clear();
   const int tile = item_tile(t);
   // j-range major: the blocks running at the same time stream the same sources through L2
-  // in the local mode `pad` is the item's first word of far-tile bits
+  // in the local mode `flag0` is the item's first word of far-tile bits
   int words = 0;
   for (int b : order)
     for (int js = 0; js < p.cl[b].split; ++js) {
