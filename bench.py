@@ -38,6 +38,13 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_INTERACTION = 20  # the paper's convention for one pair force (Sect. 4.1)
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU, 2.4 GHz)
 PEAK_FP64_TFLOPS = 78.6
+# Issue-rate ceiling of the pair loop (FP32 modes, no packed FP32): a wave64 FP32 FMA every 2.9 SIMD
+# cycles and v_rsq_f32 adding 6.2 cycles at 6 waves per SIMD (timed instruction-stream
+# microbenchmark on gfx950); VALU instructions per term of the fastest loop a workload runs, counted
+# in the compiled code (the rest of the kernel, staging, folds and near tiles, only adds to it).
+CYCLES_PER_FMA, RSQ_EXTRA_CYCLES = 2.9, 6.2
+LOOP_VALU = {("fp32dl", True): 10.19, ("fp32dl", False): 12.19, ("fp32ds", True): 17.09,
+             ("fp32ds", False): 18.09}
 METRIC = "G pair-interactions/s & %FP32 VALU peak; batched p50/p99 job latency"
 
 
@@ -369,12 +376,32 @@ def graph_ab(batch, prec, integrator, dt, steps, torch):
     return gres
 
 
-def pair_roofline(prec, inter_per_eval, pair_ms, tile=None, workload="c3"):
+def equal_masses(batch):
+    """True when every cluster's masses are all equal (the pair loops then leave the mass out)."""
+    return all(np.all(batch.mass[batch.offsets[c]:batch.offsets[c + 1]] == batch.mass[batch.offsets[c]])
+               for c in range(len(batch.offsets) - 1) if batch.offsets[c + 1] > batch.offsets[c])
+
+
+def rsq_ceiling(prec, equal_masses):
+    """The issue-rate ceiling of the fastest pair loop of this mode, as a fraction of the FP32 peak
+    (20 SIMD cycles per wave-interaction), or None where no loop count is recorded."""
+    n = LOOP_VALU.get((prec, bool(equal_masses)))
+    if n is None:
+        return None
+    cyc = n * CYCLES_PER_FMA + RSQ_EXTRA_CYCLES
+    return {"frac": round(FLOPS_PER_INTERACTION / cyc, 4), "cycles_per_wave_interaction": round(cyc, 2),
+            "valu_per_term": n, "cycles_per_fma": CYCLES_PER_FMA, "rsq_extra_cycles": RSQ_EXTRA_CYCLES}
+
+
+def pair_roofline(prec, inter_per_eval, pair_ms, tile=None, workload="c3", equal_masses=None):
     achieved = FLOPS_PER_INTERACTION * inter_per_eval / (pair_ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic_from_profile(prec, tile, workload),
-            "kernel": "pair (%s)" % prec, "kernel_ms": round(pair_ms, 4)}
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic_from_profile(prec, tile, workload),
+           "kernel": "pair (%s)" % prec, "kernel_ms": round(pair_ms, 4)}
+    if equal_masses is not None:
+        out["rsq_ceiling"] = rsq_ceiling(prec, equal_masses)
+    return out
 
 
 def extra_c1(torch):
@@ -407,7 +434,7 @@ def extra_c2(torch, steps=5):
     out = {"workload": "plummer-salpeter-65536, galaxy field, sym6, dt 2^-11", "precision_mode": prec,
            "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4),
            "G_interactions_per_s": round(ipe * 7 * steps / wall / 1e9, 3),
-           "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c2"),
+           "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c2", equal_masses(b)),
            "energy": dict(drift_report(e0, e1), steps=steps + 1)}
     out["accel_error_after_50_fp64_steps"] = sampled_state_errors(
         b, ["fp32dl", "fp32ds", "fp32c"], "sym6", dt, [50], 768, torch)["50"]
@@ -461,7 +488,7 @@ def extra_c4(torch, steps=3, base_steps=2):
     per = ipe * 7 * base_steps / el / 1e9
     return {"workload": "512 Plummer clusters, N log-uniform [256,16384], eps 1e-3, sym6", "precision_mode": prec,
             "steps": steps, "ms_per_step": round(wall / steps * 1e3, 4), "G_interactions_per_s": round(value, 3),
-            "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c4"),
+            "roofline": pair_roofline(prec, ipe, kms / max(nl, 1), tile, "c4", equal_masses(b)),
             "per_cluster_launches": {"G_interactions_per_s": round(per, 3), "steps": base_steps,
                                      "ms_per_step": round(el / base_steps * 1e3, 4)},
             "batched_over_per_cluster": round(value / per, 2),
@@ -733,7 +760,7 @@ def main():
     inter = inter_per_eval * evals_per_step * args.steps
     value = inter / wall / 1e9
     pair_ms = kms / max(nlaunch, 1)
-    roofline = pair_roofline(prec, inter_per_eval, pair_ms, tile_used, args.workload)
+    roofline = pair_roofline(prec, inter_per_eval, pair_ms, tile_used, args.workload, equal_masses(batch))
     prof = profile_summary(prec, tile_used, args.workload)
     roofline.update({
         "busy_clock_ghz_profiled": float(prof["busy_clock_ghz"]) if prof and "busy_clock_ghz" in prof else None,

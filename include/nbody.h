@@ -121,7 +121,8 @@ void nbody_destroy(nbody_ctx* ctx);
  * about 2^21/N ranges, a power of two of at most 8 with at least 256 sources each, so clusters of
  * 512..2^20 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
  * per cluster for the sort of NB_FP32DL, and for its per-item frames and far-tile bits 32 bytes per
- * 64 particles and range plus N_b^2 / 2^16 bytes per cluster, plus O(B + N/64) bookkeeping.  The workspace must be 256-byte aligned;
+ * 64 particles and range plus N_b^2 / 2^15 bytes per cluster, plus O(B + N/64) bookkeeping.  The
+ * workspace must be 256-byte aligned;
  * its contents are the library's between calls (the caller must not modify it while calls using
  * it are in flight). */
 size_t nbody_workspace_bytes(const nbody_ctx* ctx, const nbody_system* sys);
@@ -146,7 +147,7 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
  * nothing (no hipMalloc, hipFree or pinned allocation).  Same arguments, results and errors as
  * nbody_accel, and bitwise the same accelerations and potentials.  Limits: a system whose
  * nbody_workspace_bytes exceeds NB_NOALLOC_SCRATCH_BYTES (a single cluster of more than about 4.0
- * million particles, 1.6 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
+ * million particles, 1.1 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
  * than about 42,000 clusters) returns NB_ERR_ARG; these two checks run first and need
  * neither a context nor a GPU.  Every call on one GPU shares that GPU's scratch, which keeps the
  * last call's contents (the per-call counters are cleared by the call's own table upload): calls

@@ -224,12 +224,15 @@ __global__ __launch_bounds__(kBlock) void k_tileboxes(Args a, int B, int nslots)
 
 // The local frame and the far-tile bits of the pair work items (one wave per item), from the sorted
 // FP64 copy.  The frame is centred on the bounding box of the item's i-particles, ref = (lo + hi)/2,
-// with far2 = (3/4 of the box diagonal)^2 (with a 1e-6 relative margin); j-tile t of the item's
+// with far2 = (3/4 of the box diagonal D)^2 (with a 1e-6 relative margin); j-tile t of the item's
 // range is far when it is full and every one of its sources lies at |x_j - ref|^2 >= far2: then the
 // FP32 difference of two coordinates in that frame is within 1.5 x 2^-22 of the exact difference
 // (relative), and the pair kernel computes it without the double-single correction.  A tile whose
 // bounding box already lies that far (one lane per tile) is far; only the others are tested source
-// by source (the lanes split the tile's sources).  32 consecutive tiles make one word.
+// by source (the lanes split the tile's sources).  A far tile whose bounding box lies at least
+// 3/2 D from the centre is also marked for the expanded form of r^2 (the pair kernel's
+// far_tile_terms), whose rounding error grows as the sources come closer to the frame's centre.
+// Two bits per tile, 16 consecutive tiles per word: bit 2b far, bit 2b + 1 expanded.
 __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
   const int it = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (it >= a.nitems) return;
@@ -255,38 +258,45 @@ __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
     }
   const double dx = v[3] - v[0], dy = v[4] - v[1], dz = v[5] - v[2];
   const double rx = 0.5 * (v[0] + v[3]), ry = 0.5 * (v[1] + v[4]), rz = 0.5 * (v[2] + v[5]);
-  const double far2 = (dx * dx + dy * dy + dz * dz) * (0.5625 * (1.0 + 1e-6));
+  const double diag2 = dx * dx + dy * dy + dz * dz;
+  const double far2 = diag2 * (0.5625 * (1.0 + 1e-6)), farx2 = diag2 * (2.25 * (1.0 + 1e-6));
   if (lane == 0) a.ibox[it] = make_double4(rx, ry, rz, far2);
   const int T = a.jtile;
   const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
-  const int ntiles = (je - jb + T - 1) / T, nwords = (ntiles + 31) / 32;
+  const int ntiles = (je - jb + T - 1) / T, nwords = (ntiles + 15) / 16;
   const double* tb = a.tbox + 6 * ((size_t)c.tbox0 + (size_t)item.js * ((c.jlen + T - 1) / T));
   for (int q = 0; q < nwords; ++q) {
-    // box test: lane b < 32 takes tile 32 q + b
-    const int tl = 32 * q + lane;
-    bool boxfar = false, full = false;
-    if (lane < 32 && tl < ntiles) {
+    // box test: lane b < 16 takes tile 16 q + b
+    const int tl = 16 * q + lane;
+    bool boxfar = false, boxx = false, full = false;
+    if (lane < 16 && tl < ntiles) {
       full = jb + (tl + 1) * T <= je;  // a partial tile is never far
       const double* b = tb + 6 * (size_t)tl;
       const double gx = fmax(0.0, fmax(b[0] - rx, rx - b[3]));
       const double gy = fmax(0.0, fmax(b[1] - ry, ry - b[4]));
       const double gz = fmax(0.0, fmax(b[2] - rz, rz - b[5]));
-      boxfar = full && gx * gx + gy * gy + gz * gz >= far2;
+      const double g2 = gx * gx + gy * gy + gz * gz;
+      boxfar = full && g2 >= far2;
+      boxx = full && g2 >= farx2;
     }
-    unsigned word = (unsigned)__ballot(boxfar);
-    unsigned todo = (unsigned)__ballot(full && !boxfar);
+    unsigned fbits = (unsigned)__ballot(boxfar) & 0xffffu;
+    const unsigned xbits = (unsigned)__ballot(boxx) & 0xffffu;
+    unsigned todo = (unsigned)__ballot(full && !boxfar) & 0xffffu;
     while (todo) {  // full tiles the box test left open: source by source
       const int b = __ffs(todo) - 1;
       todo &= todo - 1;
-      const int j0 = jb + (32 * q + b) * T;
+      const int j0 = jb + (16 * q + b) * T;
       bool ok = true;
       for (int m = lane; m < T; m += 64) {
         const double4 p = a.spos[c.off + j0 + m];
         const double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
         ok = ok && ex * ex + ey * ey + ez * ez >= far2;
       }
-      if (__ballot(!ok) == 0ull) word |= 1u << b;
+      if (__ballot(!ok) == 0ull) fbits |= 1u << b;
     }
+    // interleave: bit 2b = far, bit 2b + 1 = expanded (only box-far tiles are expanded)
+    unsigned word = 0;
+    for (int b = 0; b < 16; ++b) word |= ((fbits >> b) & 1u) << (2 * b) | ((xbits >> b) & 1u) << (2 * b + 1);
     if (lane == 0) a.farflags[item.flag0 + q] = word;
   }
 }

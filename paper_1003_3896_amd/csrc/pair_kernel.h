@@ -24,8 +24,13 @@
 // FP32 moves the difference by at most 2^-24 (|d| + 2 R), and the FP32 subtraction by 2^-24 |d|
 // more, at most 1.5 x 2^-22 |d| in all (R = D/2 <= 2 |d|, since |d| >= 3/4 D - R), so such a term
 // is as accurate as a double-single one up to a small factor; other tiles run the double-single
-// loop.  The sort pass computes every item's frame and one far bit per j-tile beforehand, so the
-// pair kernel decides a tile with one scalar load and stages only the high parts of a far tile.
+// loop.  In equal-mass clusters a far tile whose bounding box lies at least 3/2 D from the centre
+// uses the expanded form r^2 = |x_j|^2 + |x_i|^2 - 2 x_i.x_j (one VALU instruction less per term):
+// there |x_j| >= 3 |x_i|, so every one of its six roundings is at most 2^-24 of a quantity below
+// 4 (r^2 + eps^2), a relative error of at most 24 x 2^-24 in r^2 + eps^2 (a direct FP32 r^2 has
+// about 5 x 2^-24).  The sort pass computes every item's frame and two bits per j-tile (far,
+// expanded) beforehand, so the pair kernel decides a tile with one scalar load and stages only the
+// high parts of a far tile.
 //
 // The results for a particle depend only on its own cluster's data and on (T, W) (in the local
 // family also on K, which sets the i-tile each coordinate frame is centred on): never on the other
@@ -100,6 +105,13 @@ __device__ __forceinline__ DevCluster load_cluster(const Args& a, int b) {
   return u;
 }
 
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+// Third word of a raw (untyped) buffer descriptor on gfx9-family GPUs: 32-bit data format.
+constexpr int kBufferWord3 = 0x00020000;
+__device__ __forceinline__ double as_double(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // One thread's share of a j-tile, fetched from the FP64 state into registers ahead of its use so
 // that the global-memory latency overlaps the previous tile's arithmetic.
 struct TileRaw {
@@ -107,19 +119,27 @@ struct TileRaw {
   bool valid;
 };
 
-template <int T>
-__device__ __forceinline__ TileRaw fetch_tile(const Args& a, const DevCluster& c, int j, int cnt) {
+// `off` is the cluster's first particle (c.off), passed on its own so that the local family can
+// keep it in a scalar register; SORTED: read the sorted copy (the local family always has one).
+template <int T, bool SORTED = false>
+__device__ __forceinline__ TileRaw fetch_tile(const Args& a, long long off, int j, int cnt) {
   const int tid = threadIdx.x;
   TileRaw r;
   r.valid = tid < T && tid < cnt;
-  if (r.valid && a.spos) {  // sorted copy: contiguous 32-byte records
-    const double4 q = a.spos[c.off + j + tid];
-    r.x = q.x;
-    r.y = q.y;
-    r.z = q.z;
-    r.m = q.w;
+  if (r.valid && (SORTED || a.spos)) {
+    // sorted copy: contiguous 32-byte records, read through a buffer descriptor on the tile's
+    // (scalar) base address with a 32-bit per-lane offset, so no 64-bit per-lane address stays
+    // live across the tile loop; the descriptor covers the tile's cnt records only
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(a.spos + (off + j)), (short)0, cnt * 32, kBufferWord3);
+    const v4u q0 = __builtin_amdgcn_raw_buffer_load_b128(rs, tid * 32, 0, 0);
+    const v4u q1 = __builtin_amdgcn_raw_buffer_load_b128(rs, tid * 32 + 16, 0, 0);
+    r.x = as_double(q0.x, q0.y);
+    r.y = as_double(q0.z, q0.w);
+    r.z = as_double(q1.x, q1.y);
+    r.m = as_double(q1.z, q1.w);
   } else if (r.valid) {
-    const long long g = c.off + j + tid;
+    const long long g = off + j + tid;
     r.x = a.pos[3 * g];
     r.y = a.pos[3 * g + 1];
     r.z = a.pos[3 * g + 2];
@@ -165,6 +185,19 @@ __device__ __forceinline__ void store_far_tile(PairLds<FAM, T>& sh, const TileRa
   const int tid = threadIdx.x;
   if (tid >= T) return;
   sh.hi[tid] = make_float4((float)(r.x - ref.x), (float)(r.y - ref.y), (float)(r.z - ref.z), eq ? 1.0f : (float)r.m);
+}
+
+// Writes the fetched share of a full far tile of an equal-mass cluster for the expanded form of
+// r^2 (xfar_tile_terms): -2 x_j in FP32 in the work item's frame (x_j rounded to FP32 first, then
+// scaled exactly by -2), and |x_j|^2 + eps^2 of that rounded x_j, formed in FP64 and rounded once.
+template <int FAM, int T>
+__device__ __forceinline__ void store_xfar_tile(PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref,
+                                                double eps2) {
+  const int tid = threadIdx.x;
+  if (tid >= T) return;
+  const float hx = (float)(r.x - ref.x), hy = (float)(r.y - ref.y), hz = (float)(r.z - ref.z);
+  const double c = (double)hx * hx + (double)hy * hy + (double)hz * hz + eps2;
+  sh.hi[tid] = make_float4(-2.0f * hx, -2.0f * hy, -2.0f * hz, (float)c);
 }
 
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
@@ -328,6 +361,49 @@ __device__ __forceinline__ void full_tile_terms(const LDS& sh, int u0, int j0, c
   }
 }
 
+// The pair terms of this wave's share of one LDS tile of store_xfar_tile records (equal masses, the
+// mass left out as in full_tile_terms), with r^2 in the expanded form
+//   r^2 + eps^2 = (|x_j|^2 + eps^2) + |x_i|^2 + (-2 x_j).x_i,
+// three FMAs and one add instead of three differences and three FMAs, and the sums
+// S = sum s_j (-2 x_j) and W = sum s_j, from which the caller forms sum s_j (x_j - x_i) =
+// -S/2 - x_i W in FP64.  qi = |x_i|^2 of the FP32 x_i, rounded once.
+template <int K, int TW, bool MASK, bool POT, class LDS>
+__device__ __forceinline__ void xfar_tile_terms(const LDS& sh, int u0, int j0, const float (&xi)[K],
+                                                const float (&yi)[K], const float (&zi)[K], const float (&qi)[K],
+                                                float (&ax)[K], float (&ay)[K], float (&az)[K], float (&bx)[K],
+                                                float (&by)[K], float (&bz)[K], float (&wa)[K], float (&wb)[K],
+                                                float (&pt)[K], const int (&li)[K]) {
+#pragma unroll 2
+  for (int u = u0; u < u0 + TW; u += 8) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const float4 pj = sh.hi[u + v];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float q = fmaf(pj.x, xi[k], pj.w);
+        q = fmaf(pj.y, yi[k], q);
+        q = fmaf(pj.z, zi[k], q);
+        const float r2 = q + qi[k];
+        const float inv = __builtin_amdgcn_rsqf(r2);
+        float s = inv * (inv * inv);
+        if (MASK) s = r2 > 0.0f ? s : 0.0f;
+        if (v & 1) {
+          bx[k] = fmaf(pj.x, s, bx[k]);
+          by[k] = fmaf(pj.y, s, by[k]);
+          bz[k] = fmaf(pj.z, s, bz[k]);
+          wb[k] += s;
+        } else {
+          ax[k] = fmaf(pj.x, s, ax[k]);
+          ay[k] = fmaf(pj.y, s, ay[k]);
+          az[k] = fmaf(pj.z, s, az[k]);
+          wa[k] += s;
+        }
+        if (POT) pt[k] += (j0 + u + v != li[k]) ? inv : 0.0f;
+      }
+    }
+  }
+}
+
 // PH: full tiles in phases of 8 pair terms (all coordinate differences and r^2, then the 8
 // v_rsq_f32 back to back, then the products and sums), fenced against compiler reordering, so the
 // transcendental ops of the waves sharing a SIMD can issue in pairs.
@@ -336,10 +412,18 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
   static_assert(T <= kBlock && (T / W) % 8 == 0, "tile must fit one load per thread");
   constexpr bool LOC = FAM == FAM_DL;         // local centring + near/far tiles
   constexpr bool DS = FAM == FAM_DS || LOC;  // double-single records and i-particles
+  // the expanded far-tile form: one i-particle per lane only (with two, its extra sums and |x_i|^2
+  // push the 80-register build into spilling inside the tile loop)
+  constexpr bool XF = LOC && K == 1;
   constexpr int TW = T / W;      // records per wave per tile
   __shared__ PairLds<FAM, T> sh;
   __shared__ double red[W > 1 ? 4 * 64 * K * 4 : 1];
   __shared__ int s_item;
+  // the local family parks its i-particles' low parts in LDS (each lane its own slots) and reloads
+  // them for near tiles only, which keeps three vector registers out of the far-tile loops; the
+  // slots share the memory of `red`, which is used only after the tile loop (a barrier between)
+  static_assert(!LOC || W > 1, "the local family shares red with its low-part slots");
+  float4* const s_ilo = reinterpret_cast<float4*>(red);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = wave / W, sub = wave % W;
   for (int it; (it = next_item(a, &s_item)) >= 0;) {
@@ -356,8 +440,8 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     const double mc = LOC ? a.mconst[item.cluster] : wave_uniform(a.mconst[item.cluster]);
     const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
-    float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K];
-    float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K];
+    float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K], qi[K];
+    float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K], wa[K], wb[K];
     double Ax[K], Ay[K], Az[K], Pt[K];
     int li[K];
     long long gidx[K];
@@ -374,38 +458,80 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
       xi[k] = p.x;
       yi[k] = p.y;
       zi[k] = p.z;
-      if constexpr (DS) {
+      if constexpr (LOC) {
+        s_ilo[k * kBlock + threadIdx.x] = q;
+        xl[k] = yl[k] = zl[k] = 0.0f;  // reloaded for near tiles
+      } else if constexpr (DS) {
         xl[k] = q.x;
         yl[k] = q.y;
         zl[k] = q.z;
+      } else {
+        xl[k] = yl[k] = zl[k] = 0.0f;
       }
-      if constexpr (!DS) xl[k] = yl[k] = zl[k] = 0.0f;
-      ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = pt[k] = 0.0f;
+      qi[k] = XF ? (float)((double)xi[k] * xi[k] + (double)yi[k] * yi[k] + (double)zi[k] * zi[k]) : 0.0f;
+      ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = pt[k] = wa[k] = wb[k] = 0.0f;
       Ax[k] = Ay[k] = Az[k] = Pt[k] = 0.0;
     }
     const float e2 = c.eps2f;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
-    TileRaw raw = fetch_tile<T>(a, c, jb, min(T, je - jb));
-    unsigned fw = 0;  // LOC: the far-tile bits of tiles [32 q, 32 q + 32) of this item
+    const long long coff = LOC ? wave_uniform(c.off) : c.off;
+    TileRaw raw = fetch_tile<T, LOC>(a, coff, jb, min(T, je - jb));
+    unsigned fw = 0;  // LOC: the far-tile bits of tiles [16 q, 16 q + 16) of this item
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
-      bool far = false;
+      bool far = false, xfar = false;
       if constexpr (LOC) {
         // far tile: every source at least 3/4 of the item box diagonal from its centre, so the FP32
-        // difference of the local coordinates is within 1.5 x 2^-22 relative of the exact one
-        // (bits computed by the sort pass; the same for the whole block)
+        // difference of the local coordinates is within 1.5 x 2^-22 relative of the exact one;
+        // xfar: the tile's box at least 3/2 of the diagonal away, which the expanded form of r^2
+        // needs in equal-mass clusters (bits computed by the sort pass; the same for the block)
         const int t = (j0 - jb) / T;
-        if ((t & 31) == 0) fw = a.farflags[flag0 + (t >> 5)];
-        far = (fw >> (t & 31)) & 1u;
+        if ((t & 15) == 0) fw = a.farflags[flag0 + (t >> 4)];
+        far = (fw >> (2 * (t & 15))) & 1u;
+        xfar = XF && eq && ((fw >> (2 * (t & 15) + 1)) & 1u);
       }
       __syncthreads();
-      if (LOC && far)
-        store_far_tile<FAM, T>(sh, raw, ref, eq);
-      else
+      if constexpr (LOC) {
+        if (xfar)
+          store_xfar_tile<FAM, T>(sh, raw, ref, c.eps2);
+        else if (far)
+          store_far_tile<FAM, T>(sh, raw, ref, eq);
+        else
+          store_tile<FAM, T>(a, sh, raw, ref, eq);
+      } else {
         store_tile<FAM, T>(a, sh, raw, ref, eq);
+      }
       __syncthreads();
-      if (j0 + T < je) raw = fetch_tile<T>(a, c, j0 + T, min(T, je - j0 - T));
+      if (j0 + T < je) raw = fetch_tile<T, LOC>(a, coff, j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
+      if constexpr (LOC) {
+        if (xfar) {
+          xfar_tile_terms<K, TW, MASK, POT>(sh, u0, j0, xi, yi, zi, qi, ax, ay, az, bx, by, bz, wa, wb, pt, li);
+          // sum s_j (x_j - x_i) = -(sum s_j (-2 x_j)) / 2 - x_i sum s_j, in FP64
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double w = (double)wa[k] + (double)wb[k];
+            Ax[k] += -0.5 * ((double)ax[k] + (double)bx[k]) - (double)xi[k] * w;
+            Ay[k] += -0.5 * ((double)ay[k] + (double)by[k]) - (double)yi[k] * w;
+            Az[k] += -0.5 * ((double)az[k] + (double)bz[k]) - (double)zi[k] * w;
+            ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = wa[k] = wb[k] = 0.0f;
+            if (POT) {
+              Pt[k] += (double)pt[k];
+              pt[k] = 0.0f;
+            }
+          }
+          continue;
+        }
+        if (!far) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float4 q = s_ilo[k * kBlock + threadIdx.x];
+            xl[k] = q.x;
+            yl[k] = q.y;
+            zl[k] = q.z;
+          }
+        }
+      }
       if (LOC && far && eq)
         full_tile_terms<PairLds<FAM, T>, false, K, TW, T, MASK, POT, false, true>(
             sh, u0, j0, xi, yi, zi, xl, yl, zl, e2, ax, ay, az, bx, by, bz, pt, li);
@@ -468,7 +594,14 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
         Pt[k] *= mc;
       }
     }
-    reduce_and_finish<K, W, POT>(a, c, item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+    if constexpr (LOC) {
+      // the cluster record again, so that its fields need not stay live (spilled) across the tiles
+      int cl_index = item.cluster;
+      asm volatile("" : "+v"(cl_index));
+      reduce_and_finish<K, W, POT>(a, a.cl[cl_index], item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+    } else {
+      reduce_and_finish<K, W, POT>(a, c, item, ibase, Ax, Ay, Az, Pt, red, !FOLD, kick);
+    }
   }
 }
 
@@ -547,13 +680,13 @@ __global__ __launch_bounds__(kBlock) void k_pair64(Args a, int kick) {
     }
     const double e2 = c.eps2;
     const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
-    TileRaw raw = fetch_tile<T>(a, c, jb, min(T, je - jb));
+    TileRaw raw = fetch_tile<T>(a, c.off, jb, min(T, je - jb));
     for (int j0 = jb; j0 < je; j0 += T) {
       const int cnt = min(T, je - j0);
       __syncthreads();
       store_tile<FAM_F64, T>(a, sh, raw, make_double4(0.0, 0.0, 0.0, 0.0), eq);
       __syncthreads();
-      if (j0 + T < je) raw = fetch_tile<T>(a, c, j0 + T, min(T, je - j0 - T));
+      if (j0 + T < je) raw = fetch_tile<T>(a, c.off, j0 + T, min(T, je - j0 - T));
       const int u0 = sub * TW;
       if (cnt == T && eq)
         terms64<K, T, MASK, POT, true>(sh, u0, TW, j0, xi, yi, zi, e2, ax, ay, az, pt, li);

@@ -117,7 +117,8 @@ int split_of(int n) {
 }
 
 // 32-bit words holding one bit per j-tile of T records in a j-range of len sources.
-long long flag_words(int len, int T) { return ((long long)(len + T - 1) / T + 31) / 32; }
+// far-tile words of one item's j-range: two bits per tile, 16 tiles per word
+long long flag_words(int len, int T) { return ((long long)(len + T - 1) / T + 15) / 16; }
 
 int size_class(int maxn) { return maxn < 2048 ? 0 : maxn < 32768 ? 1 : maxn < 131072 ? 2 : 3; }
 int family_of(int prec) {
@@ -298,7 +299,7 @@ int build_plan(const nbody_system* sys, Plan& p) {
       p.anysplit = true;
     }
     nitems_max += (long long)((c.n + 63) / 64) * c.split;  // the smallest item tile is 64 particles
-    // far-tile words of those items: one bit per j-tile of the item's range (tiles of at least 128)
+    // far-tile words of those items: two bits per j-tile of the item's range (tiles of at least 128)
     nflagwords += (long long)((c.n + 63) / 64) * c.split * flag_words(c.jlen, 128);
     c.tbox0 = (int)ntiles;  // the cluster's j-tile boxes: room for split ranges of tiles of >= 128
     ntiles += (long long)c.split * ((c.jlen + 127) / 128);
@@ -798,9 +799,9 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   const long long nitems = 8 * (B + n / 64);
   const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
   const long long nstiles = B + n / kSortTile;  // the sort of NB_FP32DL
-  // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/4096)
-  // <= (n/64 + B) (8 + (n + 8)/4096), since split_c <= 8 and split_c jlen_c <= n_c + split_c
-  const long long nflagwords = (n / 64 + B) * (8 + (n + 8) / 4096 + 1);
+  // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/2048)
+  // <= (n/64 + B) (8 + (n + 8)/2048), since split_c <= 8 and split_c jlen_c <= n_c + split_c
+  const long long nflagwords = (n / 64 + B) * (8 + (n + 8) / 2048 + 1);
   // j-tile boxes: sum over clusters of split_c ceil(jlen_c/128) <= n/128 + 9 B
   const long long ntiles = n / 128 + 9 * B;
   return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles, nflagwords, ntiles).total;

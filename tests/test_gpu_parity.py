@@ -337,7 +337,8 @@ def test_equal_and_nearly_equal_masses(prec):
         assert np.abs(pot[s:e] - rpot[s:e]).max() <= ptol * np.abs(rpot[s:e]).max(), c
 
 
-@pytest.mark.parametrize("tile", [(2, 4, 256, 4, 0), (2, 2, 256, 8, 0), (1, 4, 128, 8, 0), (2, 4, 128, 4, 0)])
+@pytest.mark.parametrize("tile", [(2, 4, 256, 4, 0), (2, 2, 256, 8, 0), (1, 4, 128, 8, 0), (2, 4, 128, 4, 0),
+                                  (1, 4, 256, 8, 0), (1, 2, 256, 8, 0), (1, 2, 128, 4, 0)])
 def test_local_mode_shapes_and_order(tile):
     """The Hilbert-sorted local mode returns every particle's result at its own index and meets the
     double-single bound in every compiled shape on a cluster large enough to have far tiles;
@@ -360,6 +361,29 @@ def test_local_mode_shapes_and_order(tile):
     for ncl in range(nbody.N_CLASSES):
         nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile[:3], 2, 0)
     assert np.array_equal(sim.accel().cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("tile", [(1, 4, 256, 8, 0), (2, 4, 128, 4, 0)])
+def test_local_mode_unsoftened_equal_masses(tile):
+    """eps = 0 (the self term masked) on equal masses, where most far tiles take the expanded form
+    of r^2, and a trailing one-particle item (zero box, so every full tile of it is far): the
+    accelerations meet the double-single bound and the potentials match the oracle."""
+    torch_dev()
+    from paper_1003_3896_amd import nbody
+    p, v, m = inputs.plummer(16385, 4712)
+    b = inputs.single(p, v, m, 0.0)
+    sim = make_sim(b, "fp32dl")
+    for ncl in range(nbody.N_CLASSES):
+        nbody.nbody_set_tile(sim.ctx, "fp32dl", ncl, *tile)
+    a = sim.accel(pot=True).cpu().numpy()
+    pot = sim.pot.cpu().numpy()
+    assert np.isfinite(a).all() and np.isfinite(pot).all()
+    ref, scale, rpot = oracle_reference(b, want_pot=True)
+    err = rel_errors(a, ref, scale)
+    print("\n[fp32dl eps=0 %s] %s" % (tile, stats(err)), flush=True)
+    assert err.max() <= TOL["fp32dl"]
+    assert np.median(err) <= TOL_MEDIAN["fp32dl"]
+    assert np.abs(pot - rpot).max() <= 2e-6 * np.abs(rpot).max()
 
 
 def test_local_mode_alone_equals_in_batch():

@@ -1,10 +1,14 @@
-"""The error bound of the local double-single mode's far tiles, checked by emulation on the host.
+"""The error bounds of the local double-single mode's far tiles, checked by emulation on the host.
 
 A work item centres every coordinate on the centre c of its i-particles' bounding box (diagonal
 D); a source at |x_j - c| >= 3/4 D is far and its difference to an i-particle is formed in FP32
 from the FP32-rounded local coordinates.  The claim: that difference is within 1.5 x 2^-22 |d|
 of the exact one.  The emulation rounds exactly as the kernel does (FP64 subtraction of the
-centre, rounding to FP32, FP32 subtraction) over random and worst-case placements."""
+centre, rounding to FP32, FP32 subtraction) over random and worst-case placements.
+
+In equal-mass clusters, tiles whose sources all lie at least 3/2 D from the centre form r^2 + eps^2
+in the expanded form (|x_j|^2 + eps^2) + |x_i|^2 + (-2 x_j).x_i; its six roundings give at most
+24 x 2^-24 relative error there."""
 import numpy as np
 
 BOUND = 1.5 * 2.0 ** -22
@@ -46,3 +50,70 @@ def test_the_bound_needs_the_threshold():
     xi = c + rng.uniform(-1, 1, (512, 3)) * half
     xj = xi + rng.normal(size=(512, 3)) * 1e-9                       # close pairs inside the box
     assert _local_difference_error(xi, xj, c).max() > BOUND
+
+
+XBOUND = 24.0 * 2.0 ** -24
+
+
+def _fma32(a, b, c):
+    """FP32 fused multiply-add: a*b + c formed in extended precision, rounded once to FP32."""
+    return (a.astype(np.longdouble) * b.astype(np.longdouble) + c.astype(np.longdouble)).astype(np.float32)
+
+
+def _expanded_r2_error(xi, xj, c, eps2):
+    """Relative error of the expanded r^2 + eps^2 of the pair kernel's equal-mass far tiles, against
+    the exact value for the same FP32-rounded local coordinates (the rounding of the coordinates
+    themselves is the far tiles' common error, bounded above)."""
+    li = (xi - c).astype(np.float32)
+    lj = (xj - c).astype(np.float32)
+    aj = np.float32(-2.0) * lj                                          # exact scaling
+    cj = ((lj.astype(np.float64) ** 2).sum(-1) + eps2).astype(np.float32)  # FP64, rounded once
+    qi = (li.astype(np.float64) ** 2).sum(-1).astype(np.float32)
+    q = _fma32(aj[..., 0], li[..., 0], cj)
+    q = _fma32(aj[..., 1], li[..., 1], q)
+    q = _fma32(aj[..., 2], li[..., 2], q)
+    r2 = (q.astype(np.float64) + qi.astype(np.float64)).astype(np.float32)  # FP32 add
+    d = lj.astype(np.longdouble) - li.astype(np.longdouble)
+    exact = (d * d).sum(-1) + np.longdouble(eps2)
+    return np.abs((r2.astype(np.longdouble) - exact) / exact).astype(np.float64)
+
+
+def _placements(rng, thr, n=256):
+    c = rng.uniform(-10, 10, 3)
+    half = 10.0 ** rng.uniform(-4, 0) * rng.uniform(0.2, 1.0, 3)
+    D = 2 * np.linalg.norm(half)
+    xi = c + rng.uniform(-1, 1, (n, 3)) * half
+    xi[:8] = c + np.sign(rng.uniform(-1, 1, (8, 3))) * half
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    r = thr * D * (1.0 + 10.0 ** rng.uniform(-9, 1, n))
+    # the worst alignment: sources straight out from a corner particle
+    u[:8] = (xi[:8] - c) / np.linalg.norm(xi[:8] - c, axis=1, keepdims=True)
+    return c, D, xi, c + u * r[:, None]
+
+
+def test_expanded_far_tiles_meet_their_bound():
+    """Sources at least 3/2 D from the centre: the expanded r^2 + eps^2 is within 24 x 2^-24 of the
+    exact value, with and without softening."""
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for t in range(200):
+        c, D, xi, xj = _placements(rng, 1.5)
+        eps2 = 0.0 if t % 2 else (1e-2 * D) ** 2
+        err = _expanded_r2_error(xi[:, None, :], xj[None, :, :], c, eps2)
+        worst = max(worst, float(err.max()))
+    assert worst <= XBOUND, worst
+
+
+def test_the_expanded_error_grows_toward_the_centre():
+    """The expanded form cancels more the closer the sources come to the frame's centre: its worst
+    error at the far-tile threshold of 3/4 D is several times that at 3 D (which is why it gets its
+    own, larger threshold)."""
+    def worst(thr):
+        rng = np.random.default_rng(10)
+        w = 0.0
+        for _ in range(100):
+            c, D, xi, xj = _placements(rng, thr)
+            w = max(w, float(_expanded_r2_error(xi[:, None, :], xj[None, :, :], c, 0.0).max()))
+        return w
+    assert worst(0.75) > 2.0 * worst(3.0)
