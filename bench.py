@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--ratios", default=None, help="bh: comma-separated black-hole to cluster mass ratios")
     ap.add_argument("--jobs", type=int, default=120, help="c5: jobs in the open-loop stream")
     ap.add_argument("--sat-jobs", type=int, default=48, help="c5: jobs in the closed-loop saturation run")
+    ap.add_argument("--warm-jobs", type=int, default=None,
+                    help="c5: first jobs left out of the latency statistics (default: jobs / 20)")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
     ap.add_argument("--policy", default="srpt", choices=["srpt", "all"], help="c5: which active jobs a round advances")
     ap.add_argument("--fill", type=float, default=2.0 ** 30, help="c5: pair interactions a round gathers (srpt)")
@@ -555,7 +557,7 @@ def bench_c5(args):
     el = time.perf_counter() - t0
     done = [r for r in reqs if res[r.jid].status == "done"]
     work = sum(r.interactions() for r in done)
-    warm = max(1, args.jobs // 20)
+    warm = args.warm_jobs if args.warm_jobs is not None else max(1, args.jobs // 20)
     lat = latency_stats(res, skip=warm)
     dE = [res[r.jid].rel_energy_error for r in done]
     # stretch: latency over the job's own work at the saturation rate
