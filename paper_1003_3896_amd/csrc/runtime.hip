@@ -102,10 +102,10 @@ struct Slot {
 
 // j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
 // on their own, and short enough items for the persistent grid to balance large ones (about
-// 2^21 / N ranges, a power of two, at most 8, each range at least 256 sources).
+// 2^21 / N ranges, a power of two, at most 8, each range at least 128 sources).
 // Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
 #ifndef NB_MIN_RANGE
-#define NB_MIN_RANGE 256  // fewest sources in one j-range of a split cluster (a tuning constant)
+#define NB_MIN_RANGE 128  // fewest sources in one j-range of a split cluster (a tuning constant)
 #endif
 #ifndef NB_SPLIT_CAP
 #define NB_SPLIT_CAP (1LL << 21)  // bound on N x ranges (partial sums kept per cluster)
@@ -116,7 +116,6 @@ int split_of(int n) {
   return s;
 }
 
-// 32-bit words holding one bit per j-tile of T records in a j-range of len sources.
 // far-tile words of one item's j-range: two bits per tile, 16 tiles per word
 long long flag_words(int len, int T) { return ((long long)(len + T - 1) / T + 15) / 16; }
 
