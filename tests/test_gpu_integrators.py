@@ -1,6 +1,6 @@
 """Integrator paths on the GPU: chained substeps equal single substeps, the step functions equal
 their substep sequences, the C2-like configuration (Salpeter masses, galaxy field, sym6) follows the
-oracle, and pure-FP32 mode keeps the state on FP32 values."""
+oracle, the FP32 modes follow it along C1, and pure-FP32 mode keeps the state on FP32 values."""
 import numpy as np
 import pytest
 
@@ -109,3 +109,29 @@ def test_pure_fp32_state_stays_fp32():
     for t in (s.pos, s.vel, s.acc):
         x = t.cpu().numpy()
         assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+
+
+def test_fp32_modes_follow_oracle_trajectory():
+    """The FP32 modes (FP32C: FP32 pairs on centred coordinates, FP64 state; pure FP32: FP32 state
+    too) along 10 leapfrog steps of C1 (Plummer N = 1024, eps = 1e-3, dt = 1/1024): positions within
+    1e-5 of the oracle's (relative to the largest coordinate), and the same energy error to within
+    its own size.  A sign, mass or G slip in the FP32 paths would be off by orders of magnitude."""
+    torch_dev()
+    b = inputs.c1()
+    dt, steps, eps = b.meta["dt"], 10, float(b.eps[0])
+    e0 = oracle.energy(b.pos, b.vel, b.mass, 1.0, eps, False)
+    a0 = oracle.total_accel(b.pos, b.mass, 1.0, eps, False)
+    rp, rv, _ = oracle.step(b.pos, b.vel, b.mass, a0, dt, steps, "leapfrog", 1.0, eps, False)
+    de_ref = abs(oracle.energy(rp, rv, b.mass, 1.0, eps, False)[3] - e0[3]) / abs(e0[3])
+    for prec in ("fp32c", "fp32"):
+        s = nbody.Simulation(b, prec)
+        s.accel()
+        s.step("leapfrog", dt, steps)
+        pos = s.pos.cpu().numpy()
+        rel = np.abs(pos - rp).max() / np.abs(rp).max()
+        e = s.energy(prec="fp64")[0].cpu().numpy()
+        de = abs(e[3] - e0[3]) / abs(e0[3])
+        print("\n[C1 %s] pos rel %.3e  dE/E0 %.3e (oracle %.3e)" % (prec, rel, de, de_ref), flush=True)
+        assert rel <= 1e-5
+        assert de <= 2 * de_ref + 1e-6
+        s.close()
