@@ -26,8 +26,8 @@
 // is as accurate as a double-single one up to a small factor; other tiles run the double-single
 // loop.  In equal-mass clusters a far tile whose bounding box lies at least 3/2 D from the centre
 // uses the expanded form r^2 = |x_j|^2 + |x_i|^2 - 2 x_i.x_j (one VALU instruction less per term):
-// there |x_j| >= 3 |x_i|, so every one of its six roundings is at most 2^-24 of a quantity below
-// 4 (r^2 + eps^2), a relative error of at most 24 x 2^-24 in r^2 + eps^2 (a direct FP32 r^2 has
+// there |x_j| >= 3 |x_i|, so every one of its eight roundings is at most 2^-24 of a quantity below
+// 4 (r^2 + eps^2), a relative error of at most 32 x 2^-24 in r^2 + eps^2 (a direct FP32 r^2 has
 // about 5 x 2^-24).  The sort pass computes every item's frame and two bits per j-tile (far,
 // expanded) beforehand, so the pair kernel decides a tile with one scalar load and stages only the
 // high parts of a far tile.
@@ -189,15 +189,15 @@ __device__ __forceinline__ void store_far_tile(PairLds<FAM, T>& sh, const TileRa
 
 // Writes the fetched share of a full far tile of an equal-mass cluster for the expanded form of
 // r^2 (xfar_tile_terms): -2 x_j in FP32 in the work item's frame (x_j rounded to FP32 first, then
-// scaled exactly by -2), and |x_j|^2 + eps^2 of that rounded x_j, formed in FP64 and rounded once.
+// scaled exactly by -2), and |x_j|^2 + eps^2 of that rounded x_j in three FP32 FMAs.
 template <int FAM, int T>
 __device__ __forceinline__ void store_xfar_tile(PairLds<FAM, T>& sh, const TileRaw& r, const double4& ref,
                                                 double eps2) {
   const int tid = threadIdx.x;
   if (tid >= T) return;
   const float hx = (float)(r.x - ref.x), hy = (float)(r.y - ref.y), hz = (float)(r.z - ref.z);
-  const double c = (double)hx * hx + (double)hy * hy + (double)hz * hz + eps2;
-  sh.hi[tid] = make_float4(-2.0f * hx, -2.0f * hy, -2.0f * hz, (float)c);
+  const float c = fmaf(hx, hx, fmaf(hy, hy, fmaf(hz, hz, (float)eps2)));
+  sh.hi[tid] = make_float4(-2.0f * hx, -2.0f * hy, -2.0f * hz, c);
 }
 
 // Combine the W per-wave FP64 partial sums of every group in LDS (fixed order) and finish.
@@ -366,12 +366,12 @@ __device__ __forceinline__ void full_tile_terms(const LDS& sh, int u0, int j0, c
 //   r^2 + eps^2 = (|x_j|^2 + eps^2) + |x_i|^2 + (-2 x_j).x_i,
 // three FMAs and one add instead of three differences and three FMAs, and the sums
 // S = sum s_j (-2 x_j) and W = sum s_j, from which the caller forms sum s_j (x_j - x_i) =
-// -S/2 - x_i W in FP64.  qi = |x_i|^2 of the FP32 x_i, rounded once.
+// -S/2 - x_i W in FP64.  qi = |x_i|^2 of the FP32 x_i, rounded once.  One accumulator set: the
+// other waves on the SIMD supply the parallelism (two sets measured 1.6% slower here).
 template <int K, int TW, bool MASK, bool POT, class LDS>
 __device__ __forceinline__ void xfar_tile_terms(const LDS& sh, int u0, int j0, const float (&xi)[K],
                                                 const float (&yi)[K], const float (&zi)[K], const float (&qi)[K],
-                                                float (&ax)[K], float (&ay)[K], float (&az)[K], float (&bx)[K],
-                                                float (&by)[K], float (&bz)[K], float (&wa)[K], float (&wb)[K],
+                                                float (&ax)[K], float (&ay)[K], float (&az)[K], float (&wa)[K],
                                                 float (&pt)[K], const int (&li)[K]) {
 #pragma unroll 2
   for (int u = u0; u < u0 + TW; u += 8) {
@@ -387,17 +387,10 @@ __device__ __forceinline__ void xfar_tile_terms(const LDS& sh, int u0, int j0, c
         const float inv = __builtin_amdgcn_rsqf(r2);
         float s = inv * (inv * inv);
         if (MASK) s = r2 > 0.0f ? s : 0.0f;
-        if (v & 1) {
-          bx[k] = fmaf(pj.x, s, bx[k]);
-          by[k] = fmaf(pj.y, s, by[k]);
-          bz[k] = fmaf(pj.z, s, bz[k]);
-          wb[k] += s;
-        } else {
-          ax[k] = fmaf(pj.x, s, ax[k]);
-          ay[k] = fmaf(pj.y, s, ay[k]);
-          az[k] = fmaf(pj.z, s, az[k]);
-          wa[k] += s;
-        }
+        ax[k] = fmaf(pj.x, s, ax[k]);
+        ay[k] = fmaf(pj.y, s, ay[k]);
+        az[k] = fmaf(pj.z, s, az[k]);
+        wa[k] += s;
         if (POT) pt[k] += (j0 + u + v != li[k]) ? inv : 0.0f;
       }
     }
@@ -441,7 +434,7 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
     const bool eq = mc != 0.0;
     const int ibase = item.i0 + grp * 64 * K + lane;
     float xi[K], yi[K], zi[K], xl[K], yl[K], zl[K], qi[K];
-    float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K], wa[K], wb[K];
+    float ax[K], ay[K], az[K], bx[K], by[K], bz[K], pt[K], wa[K];
     double Ax[K], Ay[K], Az[K], Pt[K];
     int li[K];
     long long gidx[K];
@@ -469,7 +462,7 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
         xl[k] = yl[k] = zl[k] = 0.0f;
       }
       qi[k] = XF ? (float)((double)xi[k] * xi[k] + (double)yi[k] * yi[k] + (double)zi[k] * zi[k]) : 0.0f;
-      ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = pt[k] = wa[k] = wb[k] = 0.0f;
+      ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = pt[k] = wa[k] = 0.0f;
       Ax[k] = Ay[k] = Az[k] = Pt[k] = 0.0;
     }
     const float e2 = c.eps2f;
@@ -506,15 +499,15 @@ __device__ __forceinline__ void pair32_items(const Args& a, int kick) {
       const int u0 = sub * TW;
       if constexpr (LOC) {
         if (xfar) {
-          xfar_tile_terms<K, TW, MASK, POT>(sh, u0, j0, xi, yi, zi, qi, ax, ay, az, bx, by, bz, wa, wb, pt, li);
+          xfar_tile_terms<K, TW, MASK, POT>(sh, u0, j0, xi, yi, zi, qi, ax, ay, az, wa, pt, li);
           // sum s_j (x_j - x_i) = -(sum s_j (-2 x_j)) / 2 - x_i sum s_j, in FP64
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            const double w = (double)wa[k] + (double)wb[k];
-            Ax[k] += -0.5 * ((double)ax[k] + (double)bx[k]) - (double)xi[k] * w;
-            Ay[k] += -0.5 * ((double)ay[k] + (double)by[k]) - (double)yi[k] * w;
-            Az[k] += -0.5 * ((double)az[k] + (double)bz[k]) - (double)zi[k] * w;
-            ax[k] = ay[k] = az[k] = bx[k] = by[k] = bz[k] = wa[k] = wb[k] = 0.0f;
+            const double w = (double)wa[k];
+            Ax[k] += -0.5 * (double)ax[k] - (double)xi[k] * w;
+            Ay[k] += -0.5 * (double)ay[k] - (double)yi[k] * w;
+            Az[k] += -0.5 * (double)az[k] - (double)zi[k] * w;
+            ax[k] = ay[k] = az[k] = wa[k] = 0.0f;
             if (POT) {
               Pt[k] += (double)pt[k];
               pt[k] = 0.0f;

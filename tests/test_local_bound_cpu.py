@@ -7,8 +7,8 @@ of the exact one.  The emulation rounds exactly as the kernel does (FP64 subtrac
 centre, rounding to FP32, FP32 subtraction) over random and worst-case placements.
 
 In equal-mass clusters, tiles whose sources all lie at least 3/2 D from the centre form r^2 + eps^2
-in the expanded form (|x_j|^2 + eps^2) + |x_i|^2 + (-2 x_j).x_i; its six roundings give at most
-24 x 2^-24 relative error there."""
+in the expanded form (|x_j|^2 + eps^2) + |x_i|^2 + (-2 x_j).x_i; its eight roundings give at most
+32 x 2^-24 relative error there."""
 import numpy as np
 
 BOUND = 1.5 * 2.0 ** -22
@@ -52,7 +52,7 @@ def test_the_bound_needs_the_threshold():
     assert _local_difference_error(xi, xj, c).max() > BOUND
 
 
-XBOUND = 24.0 * 2.0 ** -24
+XBOUND = 32.0 * 2.0 ** -24
 
 
 def _fma32(a, b, c):
@@ -67,14 +67,15 @@ def _expanded_r2_error(xi, xj, c, eps2):
     li = (xi - c).astype(np.float32)
     lj = (xj - c).astype(np.float32)
     aj = np.float32(-2.0) * lj                                          # exact scaling
-    cj = ((lj.astype(np.float64) ** 2).sum(-1) + eps2).astype(np.float32)  # FP64, rounded once
+    e2 = np.full(lj.shape[:-1], np.float32(eps2), np.float32)
+    cj = _fma32(lj[..., 0], lj[..., 0], _fma32(lj[..., 1], lj[..., 1], _fma32(lj[..., 2], lj[..., 2], e2)))
     qi = (li.astype(np.float64) ** 2).sum(-1).astype(np.float32)
     q = _fma32(aj[..., 0], li[..., 0], cj)
     q = _fma32(aj[..., 1], li[..., 1], q)
     q = _fma32(aj[..., 2], li[..., 2], q)
     r2 = (q.astype(np.float64) + qi.astype(np.float64)).astype(np.float32)  # FP32 add
     d = lj.astype(np.longdouble) - li.astype(np.longdouble)
-    exact = (d * d).sum(-1) + np.longdouble(eps2)
+    exact = (d * d).sum(-1) + np.longdouble(np.float32(eps2))  # the kernel's eps^2 is rounded to FP32
     return np.abs((r2.astype(np.longdouble) - exact) / exact).astype(np.float64)
 
 
@@ -93,7 +94,7 @@ def _placements(rng, thr, n=256):
 
 
 def test_expanded_far_tiles_meet_their_bound():
-    """Sources at least 3/2 D from the centre: the expanded r^2 + eps^2 is within 24 x 2^-24 of the
+    """Sources at least 3/2 D from the centre: the expanded r^2 + eps^2 is within 32 x 2^-24 of the
     exact value, with and without softening."""
     rng = np.random.default_rng(9)
     worst = 0.0
