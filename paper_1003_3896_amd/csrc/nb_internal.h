@@ -52,7 +52,8 @@ constexpr int kEnergySums = 17;
 constexpr int kEnergyOut = 20;
 
 // Pair work item: one i-tile of one cluster against one j-range (js) of it.  In the local mode
-// `flag0` is the item's first word of far-tile bits (bit t of the item's words: its j-tile t is far).
+// `flag0` is the item's first word of far-tile bits (bits 2t and 2t + 1 of the item's words: its
+// j-tile t is far, and far enough for the expanded form of r^2).
 struct PairItem {
   int cluster, i0, js, flag0;
 };
