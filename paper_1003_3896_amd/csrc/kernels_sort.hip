@@ -222,17 +222,27 @@ __global__ __launch_bounds__(kBlock) void k_tileboxes(Args a, int B, int nslots)
     if (lane == d) out[d] = v[d];
 }
 
+// The 16 low bits of x moved to the even bit positions 0, 2, .., 30.
+__device__ __forceinline__ unsigned spread_even(unsigned x) {
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
 // The local frame and the far-tile bits of the pair work items (one wave per item), from the sorted
 // FP64 copy.  The frame is centred on the bounding box of the item's i-particles, ref = (lo + hi)/2,
 // with far2 = (3/4 of the box diagonal D)^2 (with a 1e-6 relative margin); j-tile t of the item's
 // range is far when it is full and every one of its sources lies at |x_j - ref|^2 >= far2: then the
 // FP32 difference of two coordinates in that frame is within 1.5 x 2^-22 of the exact difference
 // (relative), and the pair kernel computes it without the double-single correction.  A tile whose
-// bounding box already lies that far (one lane per tile) is far; only the others are tested source
-// by source (the lanes split the tile's sources).  A far tile whose bounding box lies at least
-// 3/2 D from the centre is also marked for the expanded form of r^2 (the pair kernel's
-// far_tile_terms), whose rounding error grows as the sources come closer to the frame's centre.
-// Two bits per tile, 16 consecutive tiles per word: bit 2b far, bit 2b + 1 expanded.
+// bounding box already lies that far (one lane per tile, 64 tiles per pass) is far; only the others
+// are tested source by source (four tiles at a time, 16 lanes each, so that their loads are in
+// flight together).  A far tile whose bounding box lies at least 3/2 D from the centre is also
+// marked for the expanded form of r^2 (the pair kernel's xfar_tile_terms), whose rounding error
+// grows as the sources come closer to the frame's centre.  Two bits per tile, 16 consecutive tiles
+// per word: bit 2b far, bit 2b + 1 expanded.
 __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
   const int it = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (it >= a.nitems) return;
@@ -265,11 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
   const int jb = item.js * c.jlen, je = min(c.n, jb + c.jlen);
   const int ntiles = (je - jb + T - 1) / T, nwords = (ntiles + 15) / 16;
   const double* tb = a.tbox + 6 * ((size_t)c.tbox0 + (size_t)item.js * ((c.jlen + T - 1) / T));
-  for (int q = 0; q < nwords; ++q) {
-    // box test: lane b < 16 takes tile 16 q + b
-    const int tl = 16 * q + lane;
+  for (int q = 0; 16 * 4 * q < ntiles; ++q) {
+    // box test: lane b takes tile 64 q + b
+    const int tl = 64 * q + lane;
     bool boxfar = false, boxx = false, full = false;
-    if (lane < 16 && tl < ntiles) {
+    if (tl < ntiles) {
       full = jb + (tl + 1) * T <= je;  // a partial tile is never far
       const double* b = tb + 6 * (size_t)tl;
       const double gx = fmax(0.0, fmax(b[0] - rx, rx - b[3]));
@@ -279,25 +289,42 @@ __global__ __launch_bounds__(kBlock) void k_farflags(Args a) {
       boxfar = full && g2 >= far2;
       boxx = full && g2 >= farx2;
     }
-    unsigned fbits = (unsigned)__ballot(boxfar) & 0xffffu;
-    const unsigned xbits = (unsigned)__ballot(boxx) & 0xffffu;
-    unsigned todo = (unsigned)__ballot(full && !boxfar) & 0xffffu;
-    while (todo) {  // full tiles the box test left open: source by source
-      const int b = __ffs(todo) - 1;
-      todo &= todo - 1;
-      const int j0 = jb + (16 * q + b) * T;
+    unsigned long long fbits = __ballot(boxfar);
+    const unsigned long long xbits = __ballot(boxx);
+    unsigned long long todo = __ballot(full && !boxfar);
+    // full tiles the box test left open, source by source, four at a time: the lanes of quarter g
+    // take the g-th of them, every lane a sixteenth of its sources
+    const int g = lane >> 4, r = lane & 15;
+    while (todo) {
+      int t[4] = {-1, -1, -1, -1};  // wave-uniform: the next (up to) four open tiles
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        if (todo) {
+          t[h] = __ffsll(todo) - 1;
+          todo &= todo - 1;
+        }
+      const int mine = g == 0 ? t[0] : g == 1 ? t[1] : g == 2 ? t[2] : t[3];
       bool ok = true;
-      for (int m = lane; m < T; m += 64) {
-        const double4 p = a.spos[c.off + j0 + m];
-        const double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
-        ok = ok && ex * ex + ey * ey + ez * ez >= far2;
+      if (mine >= 0) {
+        const int j0 = jb + (64 * q + mine) * T;
+        for (int m = r; m < T; m += 16) {
+          const double4 p = a.spos[c.off + j0 + m];
+          const double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
+          ok = ok && ex * ex + ey * ey + ez * ez >= far2;
+        }
       }
-      if (__ballot(!ok) == 0ull) fbits |= 1u << b;
+      const unsigned long long bad = __ballot(!ok);
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        if (t[h] >= 0 && ((bad >> (16 * h)) & 0xffffull) == 0) fbits |= 1ull << t[h];
     }
-    // interleave: bit 2b = far, bit 2b + 1 = expanded (only box-far tiles are expanded)
-    unsigned word = 0;
-    for (int b = 0; b < 16; ++b) word |= ((fbits >> b) & 1u) << (2 * b) | ((xbits >> b) & 1u) << (2 * b + 1);
-    if (lane == 0) a.farflags[item.flag0 + q] = word;
+    // words 4 q .. 4 q + 3 (16 tiles each): bit 2b = far, bit 2b + 1 = expanded (only box-far
+    // tiles are expanded)
+    const int w = 4 * q + lane;
+    if (lane < 4 && w < nwords) {
+      a.farflags[item.flag0 + w] = spread_even((unsigned)(fbits >> (16 * lane)) & 0xffffu) |
+                                   (spread_even((unsigned)(xbits >> (16 * lane)) & 0xffffu) << 1);
+    }
   }
 }
 
