@@ -386,6 +386,25 @@ def test_local_mode_unsoftened_equal_masses(tile):
     assert np.abs(pot - rpot).max() <= 2e-6 * np.abs(rpot).max()
 
 
+def test_local_mode_coincident_particles():
+    """Items whose particles all sit at one point (a zero box: every full tile is far and expanded,
+    the frame centred on that point) and sources coincident with them, softened: the local mode
+    meets the double-single bound against the oracle."""
+    torch_dev()
+    p, v, m = inputs.plummer(3000, 4713)
+    p = p.copy()
+    p[:200] = p[0]            # 200 particles at one point (three whole items and part of a fourth)
+    p[1500:1520] = p[0]       # and some sources far away in the order at the same point
+    b = inputs.single(p, v, m, 1e-3)
+    sim = make_sim(b, "fp32dl")
+    a = sim.accel().cpu().numpy()
+    assert np.isfinite(a).all()
+    ref, scale = oracle_reference(b)
+    err = rel_errors(a, ref, scale)
+    print("\n[fp32dl coincident] %s" % stats(err), flush=True)
+    assert err.max() <= TOL["fp32dl"]
+
+
 def test_local_mode_alone_equals_in_batch():
     """With one launch shape for every size class, a cluster's local-mode result (sort, item
     boxes, near/far choices) is bitwise the same alone and in a ragged batch."""
