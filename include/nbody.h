@@ -118,8 +118,8 @@ void nbody_destroy(nbody_ctx* ctx);
 /* Bytes of device workspace the calls below need for `sys` (0 if `sys` is invalid; then
  * nbody_last_error() says why): 32 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
- * about 2^21/N ranges, a power of two of at most 8 with at least 128 sources each, so clusters of
- * 256..2^20 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
+ * about 2^22/N ranges, a power of two of at most 8 (16 from 2^15 particles on) with at least 128
+ * sources each, so clusters of 256..2^21 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
  * per cluster for the sort of NB_FP32DL, and for its per-item frames and far-tile bits 32 bytes per
  * 64 particles and range plus N_b^2 / 2^15 bytes per cluster, plus O(B + N/64) bookkeeping.  The
  * workspace must be 256-byte aligned;
@@ -146,14 +146,14 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
  * staging buffer of NB_NOALLOC_TABLE_BYTES that nbody_create allocated.  The call itself allocates
  * nothing (no hipMalloc, hipFree or pinned allocation).  Same arguments, results and errors as
  * nbody_accel, and bitwise the same accelerations and potentials.  Limits: a system whose
- * nbody_workspace_bytes exceeds NB_NOALLOC_SCRATCH_BYTES (a single cluster of more than about 4.0
- * million particles, 1.1 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
+ * nbody_workspace_bytes exceeds NB_NOALLOC_SCRATCH_BYTES (a single cluster of more than about 8.1
+ * million particles, 1.4 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
  * than about 42,000 clusters) returns NB_ERR_ARG; these two checks run first and need
  * neither a context nor a GPU.  Every call on one GPU shares that GPU's scratch, which keeps the
  * last call's contents (the per-call counters are cleared by the call's own table upload): calls
  * that overlap on one GPU (several streams, threads or contexts at once) race and give wrong
  * results, so order them on one stream.  Asynchronous. */
-#define NB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+#define NB_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 #define NB_NOALLOC_TABLE_BYTES ((size_t)4 << 20)
 int nbody_accel_noalloc(nbody_ctx* ctx, const nbody_system* sys, const double* pos, const double* mass,
                         double* acc, double* pot, void* stream);

@@ -102,17 +102,21 @@ struct Slot {
 
 // j-ranges a cluster's sum is split into: enough work items for small clusters to occupy the chip
 // on their own, and short enough items for the persistent grid to balance large ones (about
-// 2^21 / N ranges, a power of two, at most 8, each range at least 128 sources).
+// 2^22 / N ranges, a power of two, at most 8 below 2^15 particles and at most 16 from there on,
+// each range at least 128 sources).
 // Depends on N only, so a cluster's arithmetic never depends on the batch it is in.
 #ifndef NB_MIN_RANGE
 #define NB_MIN_RANGE 128  // fewest sources in one j-range of a split cluster (a tuning constant)
 #endif
 #ifndef NB_SPLIT_CAP
-#define NB_SPLIT_CAP (1LL << 21)  // bound on N x ranges (partial sums kept per cluster)
+#define NB_SPLIT_CAP (1LL << 22)  // bound on N x ranges (partial sums kept per cluster)
 #endif
+constexpr int kMaxSplit = 16;          // ranges of clusters of at least kSplit16 particles
+constexpr int kSplit16 = 1 << 15;      // (smaller clusters: at most 8)
 int split_of(int n) {
+  const int smax = n >= kSplit16 ? kMaxSplit : 8;
   int s = 1;
-  while (s < 8 && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
+  while (s < smax && (long long)n * (2 * s) <= NB_SPLIT_CAP && n / (2 * s) >= NB_MIN_RANGE) s *= 2;
   return s;
 }
 
@@ -792,17 +796,17 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
     return 0;
   }
   const long long n = max_particles, B = max_clusters;
-  // sum ceil(n_c/256) <= B + n/256; sum ceil(n_c/64) split_c <= 8 (B + n/64);
-  // sum split_c n_c <= min(8 n, B NB_SPLIT_CAP) (split_c n_c <= NB_SPLIT_CAP whenever split_c > 1)
+  // sum ceil(n_c/256) <= B + n/256; sum ceil(n_c/64) split_c <= 16 (B + n/64);
+  // sum split_c n_c <= min(16 n, B NB_SPLIT_CAP) (split_c n_c <= NB_SPLIT_CAP whenever split_c > 1)
   const long long nchunks = B + n / kChunk;
-  const long long nitems = 8 * (B + n / 64);
-  const long long npart = std::min(8 * n, B * (long long)NB_SPLIT_CAP);
+  const long long nitems = kMaxSplit * (B + n / 64);
+  const long long npart = std::min(kMaxSplit * n, B * (long long)NB_SPLIT_CAP);
   const long long nstiles = B + n / kSortTile;  // the sort of NB_FP32DL
   // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/2048)
-  // <= (n/64 + B) (8 + (n + 8)/2048), since split_c <= 8 and split_c jlen_c <= n_c + split_c
-  const long long nflagwords = (n / 64 + B) * (8 + (n + 8) / 2048 + 1);
-  // j-tile boxes: sum over clusters of split_c ceil(jlen_c/128) <= n/128 + 9 B
-  const long long ntiles = n / 128 + 9 * B;
+  // <= (n/64 + B) (16 + (n + 16)/2048), since split_c <= 16 and split_c jlen_c <= n_c + split_c
+  const long long nflagwords = (n / 64 + B) * (kMaxSplit + (n + kMaxSplit) / 2048 + 1);
+  // j-tile boxes: sum over clusters of split_c ceil(jlen_c/128) <= n/128 + 17 B
+  const long long ntiles = n / 128 + (kMaxSplit + 1) * B;
   return make_layout((int)B, n, (int)nchunks, nitems, npart, (int)nstiles, nflagwords, ntiles).total;
 }
 

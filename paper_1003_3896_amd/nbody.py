@@ -29,7 +29,7 @@ EXPORTS = (
     "nbody_sym6_coefficients", "nbody_substeps", "nbody_workspace_bytes_max", "nbody_accel_noalloc",
 )
 # limits of nbody_accel_noalloc (NB_NOALLOC_SCRATCH_BYTES, NB_NOALLOC_TABLE_BYTES in include/nbody.h)
-NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_SCRATCH_BYTES = 256 << 20
 NOALLOC_TABLE_BYTES = 4 << 20
 
 ENERGY_FIELDS = ("K", "W", "Uext", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "Tx", "Ty", "Tz", "M",

@@ -10,7 +10,7 @@ from paper_1003_3896_amd import autotune, inputs, nbody
 def test_noalloc_limits_are_host_checks():
     """Systems beyond the scratch or the table limit are rejected before anything else (no context,
     no GPU needed); a system within both reaches the context check."""
-    too_big = nbody.System([0, 5_000_000], [1e-3])
+    too_big = nbody.System([0, 9_000_000], [1e-3])
     with pytest.raises(nbody.NBodyError, match="scratch"):
         nbody.nbody_accel_noalloc(None, too_big, None, None, None, None, 0)
     too_many = nbody.System(np.arange(60001), np.full(60000, 1e-3))
