@@ -112,3 +112,14 @@ def test_workspace_bound_holds_for_random_batches():
         ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3, prec=prec))
         cap = int(offs[-1]) + int(rng.integers(0, 1000))
         assert ws <= nbody.nbody_workspace_bytes_max(cap, B + int(rng.integers(0, 5)))
+
+
+def test_workspace_bound_at_split_boundaries():
+    """Single clusters and batches at the sizes where the number of j-ranges changes (2^15, 2^21)
+    stay within the batch-independent bound in every precision mode."""
+    for sizes in ([32767], [32768], [262144], [2 ** 21], [2 ** 21 + 1], [3_000_000], [32768] * 40,
+                  [255, 256, 32767, 32768, 65536]):
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        for prec in ("fp32ds", "fp32dl", "fp64"):
+            ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3, prec=prec))
+            assert ws <= nbody.nbody_workspace_bytes_max(int(offs[-1]), len(sizes)), (sizes, prec)
