@@ -148,7 +148,7 @@ int nbody_accel(nbody_ctx* ctx, const nbody_system* sys, const double* pos, cons
  * nbody_accel, and bitwise the same accelerations and potentials.  Limits: a system whose
  * nbody_workspace_bytes exceeds NB_NOALLOC_SCRATCH_BYTES (a single cluster of more than about 8.1
  * million particles, 1.4 million in NB_FP32DL) or whose tables exceed NB_NOALLOC_TABLE_BYTES (more
- * than about 42,000 clusters) returns NB_ERR_ARG; these two checks run first and need
+ * than about 39,000 clusters) returns NB_ERR_ARG; these two checks run first and need
  * neither a context nor a GPU.  Every call on one GPU shares that GPU's scratch, which keeps the
  * last call's contents (the per-call counters are cleared by the call's own table upload): calls
  * that overlap on one GPU (several streams, threads or contexts at once) race and give wrong
