@@ -363,14 +363,16 @@ def test_local_mode_shapes_and_order(tile):
     assert np.array_equal(sim.accel().cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("masses", ["equal", "salpeter"])
 @pytest.mark.parametrize("tile", [(1, 4, 256, 8, 0), (2, 4, 128, 4, 0)])
-def test_local_mode_unsoftened_equal_masses(tile):
-    """eps = 0 (the self term masked) on equal masses, where most far tiles take the expanded form
-    of r^2, and a trailing one-particle item (zero box, so every full tile of it is far): the
-    accelerations meet the double-single bound and the potentials match the oracle."""
+def test_local_mode_unsoftened(tile, masses):
+    """eps = 0 (the self term masked), with equal masses (where most far tiles take the expanded
+    form of r^2 with one particle per lane) and with Salpeter masses (the direct far-tile loop with
+    a mass per source), and a trailing one-particle item (zero box, so every full tile of it is
+    far): the accelerations meet the double-single bound and the potentials match the oracle."""
     torch_dev()
     from paper_1003_3896_amd import nbody
-    p, v, m = inputs.plummer(16385, 4712)
+    p, v, m = inputs.plummer(16385, 4712, salpeter=masses == "salpeter")
     b = inputs.single(p, v, m, 0.0)
     sim = make_sim(b, "fp32dl")
     for ncl in range(nbody.N_CLASSES):
@@ -380,7 +382,7 @@ def test_local_mode_unsoftened_equal_masses(tile):
     assert np.isfinite(a).all() and np.isfinite(pot).all()
     ref, scale, rpot = oracle_reference(b, want_pot=True)
     err = rel_errors(a, ref, scale)
-    print("\n[fp32dl eps=0 %s] %s" % (tile, stats(err)), flush=True)
+    print("\n[fp32dl eps=0 %s %s] %s" % (tile, masses, stats(err)), flush=True)
     assert err.max() <= TOL["fp32dl"]
     assert np.median(err) <= TOL_MEDIAN["fp32dl"]
     assert np.abs(pot - rpot).max() <= 2e-6 * np.abs(rpot).max()
