@@ -2,13 +2,14 @@
 """Benchmark of the direct-summation hot path on one MI355X.
 
 Default workload: a single Plummer cluster of N = 262144 equal masses (eps = 1e-4, no external
-field) advanced by the kick-drift-kick leapfrog with dt = 2^-11, pair arithmetic in FP32 with
-double-single coordinates and FP64-folded tile sums (mode fp32ds).  One "step" = one leapfrog step
-= one full force evaluation (N^2 pair interactions, j = i counted as the paper counts N^2) plus
-the O(N) kick/drift/pack kernels.  Throughput is pair interactions per second of the whole step.
+field) advanced by the kick-drift-kick leapfrog with dt = 2^-11, pair arithmetic in mode fp32dl
+(particles sorted along a Hilbert curve, coordinates local to each work item, FP32 on far j-tiles
+and double-single on near ones, FP64-folded tile sums).  One "step" = one leapfrog step = one full
+force evaluation (N^2 pair interactions, j = i counted as the paper counts N^2) plus the O(N)
+sort, far-tile and kick/drift kernels.  Throughput is pair interactions per second of the whole step.
 
 Prints ONE JSON line.  Besides the contract fields it carries:
-  roofline      the pair kernel (dominant, >99% of the step) against the FP32 vector peak, with
+  roofline      the pair kernel (dominant, about 98% of the step) against the FP32 vector peak, with
                 its duration measured by HIP events recorded around every pair-kernel launch on
                 the stream the kernel runs on, over the timed region;
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample of the same
@@ -64,7 +65,7 @@ def parse():
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load as a fraction of saturation")
     ap.add_argument("--policy", default="srpt", choices=["srpt", "all"], help="c5: which active jobs a round advances")
     ap.add_argument("--fill", type=float, default=2.0 ** 30, help="c5: pair interactions a round gathers (srpt)")
-    ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp64")
+    ap.add_argument("--prec", default=None, help="fp32 | fp32c | fp32ds | fp32dl | fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
