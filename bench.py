@@ -720,7 +720,7 @@ def bench_black_hole(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU split is not part of this build "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(asked for --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "c5":

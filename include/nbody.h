@@ -72,7 +72,7 @@ enum {
   NB_ERR_ARG = -1,         /* invalid argument; nothing was launched */
   NB_ERR_HIP = -2,         /* a HIP runtime call failed */
   NB_ERR_NOMEM = -3,       /* host-side allocation failed, or workspace too small */
-  NB_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+  NB_ERR_UNSUPPORTED = -4, /* valid request the library does not implement */
   NB_ERR_NONFINITE = -5    /* not returned: nbody_energy is asynchronous and cannot see its own
                               sums, so it reports non-finite ones in its output (flag out[b][19]) */
 };
