@@ -101,10 +101,10 @@ def _p(a):
 
 
 def _gal(galaxy):
-    """Galaxy parameters as the C side reads them: (Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh); a
-    7-tuple has no central black hole."""
+    """Galaxy parameters as the C side reads them: (Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh, model,
+    Mh, ah, rcut); a 7-tuple has no central black hole, and a tuple of 9 or fewer is model 0."""
     g = list(GALAXY if galaxy is None else galaxy)
-    return _f64(g + [0.0] * (9 - len(g)))
+    return _f64(g + [0.0] * (13 - len(g)))
 
 
 def num_threads() -> int:

@@ -109,25 +109,51 @@ void oracle_accel(int64_t n, const double* pos, const double* mass, double G, do
 }
 
 /*
- * External galactic field.  gal = {Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh}.
+ * External galactic field.  gal = {Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh, model, Mh, ah, rcut}.
+ * model 0:
  *   Hernquist bulge:      Phi_b = -G Mb / (r + ab)
  *   Miyamoto-Nagai disk:  Phi_d = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
  *   logarithmic halo:     Phi_h =  vh^2 / 2 * ln(r^2 + dh^2)
+ * model 1, the Galaxy of Allen & Santillan (1991) that Sect. 3 names (spherical bulge and halo,
+ * axisymmetric disk):
+ *   bulge:                Phi_b = -G Mb / sqrt(r^2 + ab^2)
+ *   Miyamoto-Nagai disk:  as in model 0
+ *   halo:                 mass inside r, M(r) = Mh (r/ah)^2.02 / (1 + (r/ah)^1.02), for r < rcut and
+ *                         M(rcut) beyond; the potential is -G M(r)/r plus the integral of G M(s)/s^2
+ *                         from r to rcut, which is -G Mh / (1.02 ah) [H(rcut) - H(r)] with
+ *                         H(s) = ln(1 + (s/ah)^1.02) - 1.02 / (1 + (s/ah)^1.02); beyond rcut
+ *                         -G M(rcut) / r
+ * both models:
  *   central black hole:   Phi_bh = -G Mbh / sqrt(r^2 + ebh^2)  (a fixed point mass at the galaxy
  *                         centre, softened like a star; the massive point of Sect. 6.2)
  * with R^2 = x^2 + y^2, r^2 = R^2 + z^2.  Acceleration is -grad Phi, written out per component.
  * acc/phi may be NULL.
  */
+static double as91_halo_mass(double r, double Mh, double ah, double rcut) {
+  const double s = r < rcut ? r : rcut;
+  const double q = pow(s / ah, 1.02);
+  return Mh * (s / ah) * q / (1.0 + q);
+}
+
+static double as91_H(double s, double ah) {
+  const double q = pow(s / ah, 1.02);
+  return log(1.0 + q) - 1.02 / (1.0 + q);
+}
 static void ext_one(const double* x, double G, const double* gal, double* a, double* phi) {
   const double Mb = gal[0], ab = gal[1], Md = gal[2], ad = gal[3], bd = gal[4], vh = gal[5], dh = gal[6];
   const double Mbh = gal[7], ebh = gal[8];
+  const int as91 = gal[9] == 1.0;
+  const double Mh = gal[10], ah = gal[11], rcut = gal[12];
   const double X = x[0], Y = x[1], Z = x[2];
   const double R2 = X * X + Y * Y;
   const double r2 = R2 + Z * Z;
   const double r = sqrt(r2);
-  /* bulge: grad Phi_b = G Mb / (r + ab)^2 * xhat */
+  /* bulge: grad Phi_b = G Mb / (r + ab)^2 * xhat (model 0), G Mb r / (r^2 + ab^2)^(3/2) * xhat (model 1) */
   double gb = 0.0; /* grad magnitude over r */
-  if (r > 0.0) gb = G * Mb / (r * (r + ab) * (r + ab));
+  if (as91)
+    gb = G * Mb / pow(r2 + ab * ab, 1.5);
+  else if (r > 0.0)
+    gb = G * Mb / (r * (r + ab) * (r + ab));
   /* disk */
   const double s = sqrt(Z * Z + bd * bd);
   const double As = ad + s;
@@ -136,8 +162,12 @@ static void ext_one(const double* x, double G, const double* gal, double* a, dou
   const double D3 = D2 * D;
   const double gdR = G * Md / D3;             /* d Phi_d / dx = gdR * x */
   const double gdz = G * Md * As / (D3 * s);  /* d Phi_d / dz = gdz * z */
-  /* halo */
-  const double gh = vh * vh / (r2 + dh * dh); /* d Phi_h / dx = gh * x */
+  /* halo: d Phi_h / dx = gh * x; in model 1 gh = G M(r) / r^3 (the field of the mass inside r) */
+  double gh;
+  if (as91)
+    gh = r > 0.0 ? G * as91_halo_mass(r, Mh, ah, rcut) / (r2 * r) : 0.0;
+  else
+    gh = vh * vh / (r2 + dh * dh);
   /* black hole: d Phi_bh / dx = G Mbh x / (r^2 + ebh^2)^(3/2) */
   const double q2 = r2 + ebh * ebh;
   const double gbh = Mbh > 0.0 ? G * Mbh / (q2 * sqrt(q2)) : 0.0;
@@ -147,9 +177,16 @@ static void ext_one(const double* x, double G, const double* gal, double* a, dou
     a[2] = -(gb * Z + gdz * Z + gh * Z + gbh * Z);
   }
   if (phi) {
-    const double pb = -G * Mb / (r + ab);
+    const double pb = as91 ? -G * Mb / sqrt(r2 + ab * ab) : -G * Mb / (r + ab);
     const double pd = -G * Md / D;
-    const double ph = 0.5 * vh * vh * log(r2 + dh * dh);
+    double ph;
+    if (!as91)
+      ph = 0.5 * vh * vh * log(r2 + dh * dh);
+    else if (r >= rcut)
+      ph = -G * as91_halo_mass(rcut, Mh, ah, rcut) / r;
+    else /* M(r)/r -> 0 at the centre, since M(r) ~ r^2.02 */
+      ph = (r > 0.0 ? -G * as91_halo_mass(r, Mh, ah, rcut) / r : 0.0) -
+           G * Mh / (1.02 * ah) * (as91_H(rcut, ah) - as91_H(r, ah));
     const double pbh = Mbh > 0.0 ? -G * Mbh / sqrt(q2) : 0.0;
     *phi = pb + pd + ph + pbh;
   }

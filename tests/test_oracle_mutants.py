@@ -24,8 +24,7 @@ MUTANTS = [
     ("drift-uses-acc", "pos[i] = pos[i] + c * vel[i];", "pos[i] = pos[i] + c * vel[i] * 0.999999;"),
     ("disk-exponent", "const double D3 = D2 * D;", "const double D3 = D2 * D2;"),
     ("disk-z-factor", "G * Md * As / (D3 * s);", "G * Md / (D3 * s);"),
-    ("halo-sign", "const double ph = 0.5 * vh * vh * log(r2 + dh * dh);",
-     "const double ph = -0.5 * vh * vh * log(r2 + dh * dh);"),
+    ("halo-sign", "ph = 0.5 * vh * vh * log(r2 + dh * dh);", "ph = -0.5 * vh * vh * log(r2 + dh * dh);"),
     ("energy-half-missing", "nsum_add(&W, 0.5 * m * pot[i]);", "nsum_add(&W, m * pot[i]);"),
     ("kinetic-half-missing", "nsum_add(&K, 0.5 * m * (v[0]", "nsum_add(&K, 1.0 * m * (v[0]"),
     ("L-index", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[0]));", "nsum_add(&L[2], m * (x[0] * v[1] - x[1] * v[1]));"),
@@ -39,6 +38,11 @@ MUTANTS = [
     ("momentum-index", "nsum_add(&P[c], m * v[c]);", "nsum_add(&P[c], m * v[0]);"),
     ("force-sum-mass-dropped", "nsum_add(&F[c], m * a[c]);", "nsum_add(&F[c], a[c]);"),
     ("force-abs-mass-dropped", "nsum_add(&A, m * sqrt(", "nsum_add(&A, sqrt("),
+    ("as91-halo-mass-power", "return Mh * (s / ah) * q / (1.0 + q);", "return Mh * q / (1.0 + q);"),
+    ("as91-bulge-power", "gb = G * Mb / pow(r2 + ab * ab, 1.5);", "gb = G * Mb / pow(r2 + ab * ab, 1.0);"),
+    ("as91-halo-potential-term", "return log(1.0 + q) - 1.02 / (1.0 + q);", "return log(1.0 + q) - 1.0 / (1.0 + q);"),
+    ("as91-beyond-cutoff", "ph = -G * as91_halo_mass(rcut, Mh, ah, rcut) / r;",
+     "ph = -G * as91_halo_mass(rcut, Mh, ah, rcut) / rcut;"),
 ]
 
 
@@ -129,6 +133,27 @@ def _pins():
     r = np.linalg.norm(p2[1] - p2[0])
     if abs(e2b[18] - 2 * m2[0] * m2[1] * r / (r * r + 0.01) ** 1.5) > 1e-15:
         fails.append("force-abs-closed-form")
+    # the Allen & Santillan Galaxy: its published circular speed, escape speed and total mass, and
+    # -grad Phi by central differences inside and beyond the halo cut-off
+    from test_oracle_field import _as91
+    g, gal = _as91()
+    a0, ph0 = oracle.ext_field(np.array([[g["R0"], 0.0, 0.0]]), galaxy=gal)
+    if abs(math.sqrt(max(-a0[0, 0] * g["R0"], 0.0)) - g["vc0"]) > 0.05:
+        fails.append("as91-circular-speed")
+    if abs(math.sqrt(max(-2.0 * ph0[0], 0.0)) - g["vesc0"]) > 0.1:
+        fails.append("as91-escape-speed")
+    _, phf = oracle.ext_field(np.array([[1e6, 0.0, 0.0]]), galaxy=gal)
+    if abs(-1e6 * phf[0] * g["mass_unit_msun"] / g["mtot_msun"] - 1.0) > 0.005:
+        fails.append("as91-total-mass")
+    pts = np.array([[0.3, 0.2, 0.1], [8.5, 0.0, 0.3], [40.0, -20.0, 5.0], [150.0, 30.0, -60.0]])
+    aa, _ = oracle.ext_field(pts, galaxy=gal)
+    fd = np.zeros_like(pts)
+    for c in range(3):
+        dp = np.zeros(3)
+        dp[c] = 1e-5
+        fd[:, c] = -(oracle.ext_field(pts + dp, galaxy=gal)[1] - oracle.ext_field(pts - dp, galaxy=gal)[1]) / 2e-5
+    if (np.linalg.norm(aa - fd, axis=1) / np.linalg.norm(aa, axis=1)).max() > 1e-7:
+        fails.append("as91-gradient")
     return fails
 
 
