@@ -79,18 +79,32 @@ enum {
 
 enum { NB_FP32 = 0, NB_FP32C = 1, NB_FP32DS = 2, NB_FP64 = 3, NB_FP32DL = 4 };
 
-/* External galaxy (Eq. 3, F_ext), G-scaled except for the halo:
+/* External galaxy (Eq. 3, F_ext).  model NB_GALAXY_HERNQUIST_LOG (0), G-scaled except the halo:
  *   Hernquist bulge      Phi_b  = -G Mb / (r + ab)
  *   Miyamoto-Nagai disk  Phi_d  = -G Md / sqrt(R^2 + (ad + sqrt(z^2 + bd^2))^2)
  *   logarithmic halo     Phi_h  = vh^2 / 2 ln(r^2 + dh^2)
+ * model NB_GALAXY_ALLEN_SANTILLAN (1), the Galaxy of Allen & Santillan (1991) that Sect. 3 names
+ * (spherical bulge and halo, axisymmetric disk), all G-scaled; vh and dh are not used:
+ *   bulge                Phi_b  = -G Mb / sqrt(r^2 + ab^2)
+ *   Miyamoto-Nagai disk  as in model 0
+ *   halo                 mass inside r  M(r) = Mh (r/ah)^2.02 / (1 + (r/ah)^1.02) for r < rcut, and
+ *                        M(rcut) beyond; Phi_h = -G M(r)/r - G Mh/(1.02 ah) [H(rcut) - H(r)] with
+ *                        H(s) = ln(1 + (s/ah)^1.02) - 1.02 / (1 + (s/ah)^1.02) for r < rcut, and
+ *                        -G M(rcut)/r beyond (its published parameters, in kpc and 2.32e7 solar
+ *                        masses with G = 1: Mb 606, ab 0.3873, Md 3690, ad 5.3178, bd 0.25,
+ *                        Mh 4615, ah 12, rcut 100)
+ * both models:
  *   central black hole   Phi_bh = -G Mbh / sqrt(r^2 + ebh^2)   (Sect. 6.2: a massive point fixed
  *                        at the galaxy centre; Mbh = 0 leaves it out)
  * with R^2 = x^2 + y^2 and r^2 = R^2 + z^2; a_ext = -grad(Phi_b + Phi_d + Phi_h + Phi_bh).
  * Mbh > 0 with ebh = 0 is singular at the origin (a particle exactly there gets a non-finite
- * acceleration, which the energy diagnostics flag). */
+ * acceleration, which the energy diagnostics flag).  Mh, ah and rcut are read by model 1 only. */
+enum { NB_GALAXY_HERNQUIST_LOG = 0, NB_GALAXY_ALLEN_SANTILLAN = 1 };
 typedef struct {
   double Mb, ab, Md, ad, bd, vh, dh;
   double Mbh, ebh;
+  int32_t model;          /* NB_GALAXY_HERNQUIST_LOG or NB_GALAXY_ALLEN_SANTILLAN */
+  double Mh, ah, rcut;    /* model 1's halo */
 } nbody_galaxy;
 
 /* A ragged batch of clusters.  All pointers are HOST pointers read during the call only. */

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Args a) {
     q[16] = m * sqrt(ax * ax + ay * ay + az * az);
     if (c.flags & kFlagField) {
       double ex, ey, ez;
-      galaxy_accel(a.gal, a.G, x, y, z, ex, ey, ez);
+      galaxy_accel<true>(a.gal, a.G, x, y, z, ex, ey, ez);
       q[2] = m * galaxy_potential(a.gal, a.G, x, y, z);
       q[9] = m * (y * ez - z * ey);
       q[10] = m * (z * ex - x * ez);
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(Args a, int potmode, int kic
   const Chunk ch = a.chunks[blockIdx.x];
   const DevCluster c = a.cl[ch.cluster];
   const int t = threadIdx.x;
-  if (c.split <= 1 || t >= ch.count) return;
+  if ((c.split <= 1 && !(c.flags & kFlagDefer)) || t >= ch.count) return;
   const int li = ch.start + t;  // position in the cluster's (sorted) order
   const long long gi = particle_index(a, c, li);
   const bool r32 = a.prec == NB_FP32;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(Args a, int potmode, int kic
     az = fz;
     pt = fp;
   }
-  finish_particle(a, c, ch.cluster, gi, ax, ay, az, r32, kick);
+  finish_particle<true>(a, c, ch.cluster, gi, ax, ay, az, r32, kick);
   if (potmode && a.pot) a.pot[gi] = r32 ? (double)(-(float)a.G * (float)pt) : -a.G * pt;
 }
 

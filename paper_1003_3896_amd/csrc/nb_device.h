@@ -55,28 +55,60 @@ __device__ __forceinline__ void block_minmax(double (&mn)[V], double (&mx)[V], d
       }
 }
 
-// External galaxy field at (X,Y,Z) in FP64 (the F_ext term of Eq. 3):
-// Hernquist bulge + Miyamoto-Nagai disk + logarithmic halo + an optional softened point mass at the
-// centre (the black hole of Sect. 6.2); acceleration = -grad Phi.
+// External galaxy field at (X,Y,Z) in FP64 (the F_ext term of Eq. 3), acceleration = -grad Phi:
+// model 0, Hernquist bulge + Miyamoto-Nagai disk + logarithmic halo; model 1, the Allen & Santillan
+// (1991) Galaxy (a spherical bulge Phi = -G Mb / sqrt(r^2 + ab^2), the same disk, and a spherical
+// halo of mass M(r) = Mh (r/ah)^2.02 / (1 + (r/ah)^1.02) inside r, constant beyond rcut); both with
+// an optional softened point mass at the centre (the black hole of Sect. 6.2).  ALL_MODELS = false
+// compiles model 0 only: the pair kernel never finishes a particle in model 1's field (those
+// clusters are finished by the combine pass), and model 1's transcendental functions would take
+// registers there.
+
+// Model 1's halo: the mass inside min(r, rcut).
+__device__ __forceinline__ double as91_halo_mass(const Galaxy& g, double r) {
+  const double s = fmin(r, g.rcut) / g.ah;
+  const double q = pow(s, 1.02);
+  return g.Mh * s * q / (1.0 + q);
+}
+
+template <bool ALL_MODELS>
 __device__ __forceinline__ void galaxy_accel(const Galaxy& g, double G, double X, double Y, double Z, double& ax,
                                              double& ay, double& az) {
   const double R2 = X * X + Y * Y;
   const double r2 = R2 + Z * Z;
   const double r = sqrt(r2);
-  const double rb = r + g.ab;
-  const double fb = r > 0.0 ? G * g.Mb / (r * rb * rb) : 0.0;  // |grad Phi_b| / r
+  double fb, fh;  // |grad Phi_b| / r and |grad Phi_h| / r
+  if (ALL_MODELS && g.model == kGalaxyAllenSantillan) {
+    const double q = r2 + g.ab * g.ab;
+    fb = G * g.Mb / (q * sqrt(q));
+    fh = r > 0.0 ? G * as91_halo_mass(g, r) / (r2 * r) : 0.0;  // the field of the mass inside r
+  } else {
+    const double rb = r + g.ab;
+    fb = r > 0.0 ? G * g.Mb / (r * rb * rb) : 0.0;
+    fh = g.vh * g.vh / (r2 + g.dh * g.dh);
+  }
   const double zs = sqrt(Z * Z + g.bd * g.bd);
   const double as = g.ad + zs;
   const double D2 = R2 + as * as;
   const double fd = G * g.Md / (D2 * sqrt(D2));                // (1/R) dPhi_d/dR
   const double fz = fd * as / zs;                               // (1/z) dPhi_d/dz
-  const double fh = g.vh * g.vh / (r2 + g.dh * g.dh);           // (1/r) dPhi_h/dr
   const double q2 = r2 + g.ebh * g.ebh;
   const double fbh = g.Mbh > 0.0 ? G * g.Mbh / (q2 * sqrt(q2)) : 0.0;  // (1/r) dPhi_bh/dr
   const double fxy = fb + fd + fh + fbh;
   ax = -fxy * X;
   ay = -fxy * Y;
   az = -(fb + fz + fh + fbh) * Z;
+}
+
+// Model 1's halo potential: -G M(r)/r minus the work against the field of the mass inside from r out
+// to rcut, G Mh / (1.02 ah) [H(rcut) - H(r)] with H(s) = ln(1 + (s/ah)^1.02) - 1.02 / (1 + (s/ah)^1.02),
+// the closed form of that integral; beyond rcut the point-mass potential of M(rcut).
+__device__ __forceinline__ double as91_halo_potential(const Galaxy& g, double G, double r) {
+  if (r >= g.rcut) return -G * as91_halo_mass(g, g.rcut) / r;
+  const double qc = pow(g.rcut / g.ah, 1.02), q = pow(r / g.ah, 1.02);
+  const double Hc = log(1.0 + qc) - 1.02 / (1.0 + qc), H = log(1.0 + q) - 1.02 / (1.0 + q);
+  const double inner = r > 0.0 ? -G * as91_halo_mass(g, r) / r : 0.0;  // M(r) ~ r^2.02 at the centre
+  return inner - G * g.Mh / (1.02 * g.ah) * (Hc - H);
 }
 
 __device__ __forceinline__ double galaxy_potential(const Galaxy& g, double G, double X, double Y, double Z) {
@@ -86,7 +118,10 @@ __device__ __forceinline__ double galaxy_potential(const Galaxy& g, double G, do
   const double zs = sqrt(Z * Z + g.bd * g.bd);
   const double as = g.ad + zs;
   const double pbh = g.Mbh > 0.0 ? -G * g.Mbh / sqrt(r2 + g.ebh * g.ebh) : 0.0;
-  return -G * g.Mb / (r + g.ab) - G * g.Md / sqrt(R2 + as * as) + 0.5 * g.vh * g.vh * log(r2 + g.dh * g.dh) + pbh;
+  const double pd = -G * g.Md / sqrt(R2 + as * as);
+  if (g.model == kGalaxyAllenSantillan)
+    return -G * g.Mb / sqrt(r2 + g.ab * g.ab) + pd + as91_halo_potential(g, G, r) + pbh;
+  return -G * g.Mb / (r + g.ab) + pd + 0.5 * g.vh * g.vh * log(r2 + g.dh * g.dh) + pbh;
 }
 
 // 1/sqrt(x) in FP64: the hardware estimate (relative error ~2^-24) refined by one
@@ -123,7 +158,8 @@ __device__ __forceinline__ double4 record64(const Args& a, long long gi) {
 }
 
 // Epilogue of one particle: scale by G, add the galaxy field (unless the pass wants the internal
-// acceleration alone), store, optional kick.
+// acceleration alone), store, optional kick.  ALL_MODELS: as in galaxy_accel.
+template <bool ALL_MODELS>
 __device__ __forceinline__ void finish_particle(const Args& a, const DevCluster& c, int cluster, long long gi,
                                                 double ax, double ay, double az, bool round32, int kick) {
   ax *= a.G;
@@ -136,7 +172,7 @@ __device__ __forceinline__ void finish_particle(const Args& a, const DevCluster&
   }
   if ((c.flags & kFlagField) && !a.internal_only) {
     double ex, ey, ez;
-    galaxy_accel(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
+    galaxy_accel<ALL_MODELS>(a.gal, a.G, a.pos[3 * gi], a.pos[3 * gi + 1], a.pos[3 * gi + 2], ex, ey, ez);
     ax += ex;
     ay += ey;
     az += ez;

@@ -25,8 +25,9 @@ constexpr int kRadix = 1 << kRadixBits;
 struct DevCluster {
   long long off;       // first particle of the cluster in the concatenated arrays
   long long part_off;  // first row of the cluster's partial sums ([split][n] rows), when split > 1
+                       // or kFlagDefer
   int n;               // particles
-  int flags;           // kFlagField | kFlagMaskSelf
+  int flags;           // kFlagField | kFlagMaskSelf | kFlagDefer
   double eps2;         // eps^2 in FP64
   float eps2f;         // eps^2 rounded to FP32
   int chunk0;          // first O(N) chunk of the cluster
@@ -40,6 +41,8 @@ struct DevCluster {
 };
 constexpr int kFlagField = 1;     // add the galaxy field
 constexpr int kFlagMaskSelf = 2;  // eps == 0: the j = i term must be excluded explicitly
+constexpr int kFlagDefer = 4;     // finished by the combine pass even when unsplit (its galaxy model
+                                  // is one the pair kernel leaves out)
 
 // O(N) chunk: kChunk consecutive particles of one cluster (also used for sort tiles of
 // kSortTile particles).
@@ -58,8 +61,12 @@ struct PairItem {
   int cluster, i0, js, flag0;
 };
 
+// Galaxy models (the values of the C interface's NB_GALAXY_* constants).
+constexpr int kGalaxyHernquistLog = 0, kGalaxyAllenSantillan = 1;
 struct Galaxy {
   double Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh;
+  int model;  // kGalaxyHernquistLog or kGalaxyAllenSantillan
+  double Mh, ah, rcut;
 };
 
 // Everything the kernels of one call need; passed by value.

@@ -240,9 +240,9 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
     }
   }
   if (sub != 0) return;
-  if (c.split > 1) {
-    // one j-range of a split cluster: the combine pass adds the ranges in range order and
-    // finishes the particles (kernel boundaries, not device-scope fences, order the two: a fence
+  if (c.split > 1 || (c.flags & kFlagDefer)) {
+    // one j-range of a split cluster (or the only range of a deferred one): the combine pass adds
+    // the ranges in range order and finishes the particles (kernel boundaries, not device-scope fences, order the two: a fence
     // inside this persistent kernel would write back and invalidate the XCD's L2)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -256,7 +256,7 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
     const int li = ibase + k * 64;
     if (li >= c.n) continue;
     const long long gi = particle_index(a, c, li);
-    finish_particle(a, c, item.cluster, gi, ax[k], ay[k], az[k], round32, kick);
+    finish_particle<false>(a, c, item.cluster, gi, ax[k], ay[k], az[k], round32, kick);
     if (POT && a.pot) a.pot[gi] = round32 ? (double)(-(float)a.G * (float)pt[k]) : -a.G * pt[k];
   }
 }

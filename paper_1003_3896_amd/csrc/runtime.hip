@@ -19,6 +19,10 @@
 
 using namespace nb;
 
+static_assert(nb::kGalaxyHernquistLog == NB_GALAXY_HERNQUIST_LOG &&
+                  nb::kGalaxyAllenSantillan == NB_GALAXY_ALLEN_SANTILLAN,
+              "galaxy model numbers of the kernels and of the C interface");
+
 namespace {
 
 thread_local std::string g_err;
@@ -86,7 +90,7 @@ struct Plan {
   int ntboxes = 0;  // j-tile box slots (NB_FP32DL only)
   int maxn = 0;
   bool anymask = false;
-  bool anysplit = false;
+  bool anysplit = false;  // some cluster is finished by the combine pass (split, or kFlagDefer)
   std::vector<DevCluster> cl;
   std::vector<Chunk> chunks;
   std::vector<Chunk> stiles;
@@ -203,12 +207,18 @@ int check_system(const nbody_system* sys) {
     for (int b = 0; b < sys->nclusters; ++b) anyfield |= sys->field[b] != 0;
   if (anyfield) {
     const nbody_galaxy& g = sys->galaxy;
-    const double v[9] = {g.Mb, g.ab, g.Md, g.ad, g.bd, g.vh, g.dh, g.Mbh, g.ebh};
+    if (g.model != NB_GALAXY_HERNQUIST_LOG && g.model != NB_GALAXY_ALLEN_SANTILLAN)
+      return fail(NB_ERR_ARG, "unknown galaxy model %d", g.model);
+    const bool as91 = g.model == NB_GALAXY_ALLEN_SANTILLAN;
+    const double v[12] = {g.Mb, g.ab, g.Md, g.ad, g.bd, g.vh, g.dh, g.Mbh, g.ebh, g.Mh, g.ah, g.rcut};
     for (double x : v)
       if (!std::isfinite(x)) return fail(NB_ERR_ARG, "galaxy parameters must be finite");
-    if (g.Mb < 0 || g.Md < 0 || g.ad < 0 || g.vh < 0 || g.Mbh < 0 || g.ebh < 0)
-      return fail(NB_ERR_ARG, "galaxy masses, ad, vh and ebh must be >= 0");
-    if (!(g.ab > 0 && g.bd > 0 && g.dh > 0)) return fail(NB_ERR_ARG, "galaxy ab, bd and dh must be > 0");
+    if (g.Mb < 0 || g.Md < 0 || g.ad < 0 || g.Mbh < 0 || g.ebh < 0)
+      return fail(NB_ERR_ARG, "galaxy masses, ad and ebh must be >= 0");
+    if (!(g.ab > 0 && g.bd > 0)) return fail(NB_ERR_ARG, "galaxy ab and bd must be > 0");
+    if (!as91 && !(g.vh >= 0 && g.dh > 0)) return fail(NB_ERR_ARG, "galaxy vh must be >= 0 and dh > 0");
+    if (as91 && !(g.Mh >= 0 && g.ah > 0 && g.rcut > 0))
+      return fail(NB_ERR_ARG, "galaxy Mh must be >= 0, ah and rcut > 0");
   }
   return NB_OK;
 }
@@ -287,6 +297,8 @@ int build_plan(const nbody_system* sys, Plan& p) {
     c.eps2 = e * e;
     c.eps2f = (float)(e * e);
     c.flags = (sys->field && sys->field[b]) ? kFlagField : 0;
+    // the pair kernel finishes particles in the first galaxy model only; the combine pass does both
+    if ((c.flags & kFlagField) && sys->galaxy.model == NB_GALAXY_ALLEN_SANTILLAN) c.flags |= kFlagDefer;
     // FP32 rounding of a tiny eps^2 to 0 would make the self term 0 * inf; mask it then too
     const bool mask = (c.eps2 == 0.0) || (sys->prec != NB_FP64 && c.eps2f == 0.0f);
     if (mask) c.flags |= kFlagMaskSelf;
@@ -296,8 +308,9 @@ int build_plan(const nbody_system* sys, Plan& p) {
     for (int s = 0; s < c.n; s += kChunk) p.chunks.push_back(Chunk{b, s, std::min(kChunk, c.n - s), 0});
     c.split = split_of(c.n);
     c.jlen = (c.n + c.split - 1) / c.split;
-    c.part_off = c.split > 1 ? npart : 0;
-    if (c.split > 1) {
+    const bool via_combine = c.split > 1 || (c.flags & kFlagDefer);
+    c.part_off = via_combine ? npart : 0;
+    if (via_combine) {
       npart += (long long)c.split * c.n;
       p.anysplit = true;
     }
@@ -466,8 +479,9 @@ int prepare(nbody_ctx* ctx, const nbody_system* sys, void* ws, size_t ws_bytes, 
   a.part = reinterpret_cast<double4*>(w + L.part);
   a.coef = coef3 ? reinterpret_cast<double*>(w + L.coef) : nullptr;
   a.G = sys->G;
-  a.gal = Galaxy{sys->galaxy.Mb, sys->galaxy.ab, sys->galaxy.Md, sys->galaxy.ad, sys->galaxy.bd,
-                 sys->galaxy.vh, sys->galaxy.dh, sys->galaxy.Mbh, sys->galaxy.ebh};
+  a.gal = Galaxy{sys->galaxy.Mb,  sys->galaxy.ab,  sys->galaxy.Md,  sys->galaxy.ad,    sys->galaxy.bd,
+                 sys->galaxy.vh,  sys->galaxy.dh,  sys->galaxy.Mbh, sys->galaxy.ebh,   sys->galaxy.model,
+                 sys->galaxy.Mh,  sys->galaxy.ah,  sys->galaxy.rcut};
   a.prec = sys->prec;
   P.tile = t;
   P.grid = std::max(1, std::min(a.nitems, ctx->cus * t.bpc));
@@ -797,10 +811,12 @@ size_t nbody_workspace_bytes_max(int64_t max_particles, int32_t max_clusters) {
   }
   const long long n = max_particles, B = max_clusters;
   // sum ceil(n_c/256) <= B + n/256; sum ceil(n_c/64) split_c <= 16 (B + n/64);
-  // sum split_c n_c <= min(16 n, B NB_SPLIT_CAP) (split_c n_c <= NB_SPLIT_CAP whenever split_c > 1)
+  // partial-sum rows: sum of split_c n_c over the clusters finished by the combine pass <=
+  // min(16 n, B NB_SPLIT_CAP + n) (split_c n_c <= NB_SPLIT_CAP whenever split_c > 1, and an unsplit
+  // cluster there, one in the second galaxy model, adds its n_c)
   const long long nchunks = B + n / kChunk;
   const long long nitems = kMaxSplit * (B + n / 64);
-  const long long npart = std::min(kMaxSplit * n, B * (long long)NB_SPLIT_CAP);
+  const long long npart = std::min(kMaxSplit * n, B * (long long)NB_SPLIT_CAP + n);
   const long long nstiles = B + n / kSortTile;  // the sort of NB_FP32DL
   // far-tile words: sum over clusters of ceil(n_c/64) split_c ceil(jlen_c/2048)
   // <= (n/64 + B) (16 + (n + 16)/2048), since split_c <= 16 and split_c jlen_c <= n_c + split_c

@@ -33,6 +33,14 @@ V_CIRC_8 = 0.837866164494
 V_CIRC_10 = 0.821107211916  # circular speed of the same galaxy at R = 10
 ORBIT_R = 8.0
 
+# The Allen & Santillan (1991) Galaxy that Sect. 3 names, as the library's second galaxy model:
+# (Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh, model, Mh, ah, rcut) with its published parameters in its
+# own units (length kpc, mass 2.32e7 solar masses, G = 1, so velocities in units of 10 km/s):
+# spherical bulge, Miyamoto-Nagai disk, spherical halo cut off at 100 kpc (vh, dh unused).
+ALLEN_SANTILLAN = (606.0, 0.3873, 3690.0, 5.3178, 0.25, 0.0, 1.0, 0.0, 0.0, 1.0, 4615.0, 12.0, 100.0)
+AS91_SUN_R = 8.5      # the solar radius of that model (kpc)
+AS91_SUN_VC = 22.0    # its circular speed there (220 km/s), pinned against the oracle's field
+
 DT_DEFAULT = 2.0 ** -11
 
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 NB_OK, NB_ERR_ARG, NB_ERR_HIP, NB_ERR_NOMEM, NB_ERR_UNSUPPORTED, NB_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 NB_FP32, NB_FP32C, NB_FP32DS, NB_FP64, NB_FP32DL = 0, 1, 2, 3, 4
+NB_GALAXY_HERNQUIST_LOG, NB_GALAXY_ALLEN_SANTILLAN = 0, 1
 PREC = {"fp32": NB_FP32, "fp32c": NB_FP32C, "fp32ds": NB_FP32DS, "fp64": NB_FP64, "fp32dl": NB_FP32DL}
 # cluster-size classes of the launch-shape table (nbody_set_tile)
 N_CLASSES = 4
@@ -44,7 +45,8 @@ class NBodyError(RuntimeError):
 
 
 class nbody_galaxy(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("Mb", "ab", "Md", "ad", "bd", "vh", "dh", "Mbh", "ebh")]
+    _fields_ = ([(n, ctypes.c_double) for n in ("Mb", "ab", "Md", "ad", "bd", "vh", "dh", "Mbh", "ebh")] +
+                [("model", ctypes.c_int32)] + [(n, ctypes.c_double) for n in ("Mh", "ah", "rcut")])
 
 
 class nbody_system(ctypes.Structure):
@@ -149,7 +151,9 @@ class System:
         self.field = None if field is None else np.ascontiguousarray(
             np.broadcast_to(np.asarray(field, np.uint8), (B,)))
         self.G = float(G)
-        self.galaxy = tuple(float(v) for v in galaxy) + (0.0,) * (9 - len(galaxy))  # no black hole if 7
+        # (Mb, ab, Md, ad, bd, vh, dh, Mbh, ebh, model, Mh, ah, rcut): no black hole if 7 values,
+        # model 0 if 9 or fewer
+        self.galaxy = tuple(float(v) for v in galaxy) + (0.0,) * (13 - len(galaxy))
         self.prec = PREC[prec] if isinstance(prec, str) else int(prec)
         c = nbody_system()
         c.nclusters = B
@@ -158,7 +162,8 @@ class System:
         c.eps = self.eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         c.field = (self.field.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if self.field is not None
                    else ctypes.POINTER(ctypes.c_uint8)())
-        c.galaxy = nbody_galaxy(*self.galaxy)
+        g = self.galaxy
+        c.galaxy = nbody_galaxy(*g[:9], int(g[9]), *g[10:])
         c.prec = self.prec
         self._c = c
 

@@ -66,6 +66,10 @@ def test_workspace_bytes_and_interactions():
     dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, float("nan"))),
     dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0, -1.0, 0.0)),  # Mbh < 0
     dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0, 5.0, float("inf"))),
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(1, 0.7, 4.5, 3.0, 0.28, 0.7, 12.0, 0, 0, 2, 0, 0, 0)),  # model
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(606, 0.39, 3690, 5.3, 0.25, 0, 0, 0, 0, 1, 4615, 0.0, 100)),
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(606, 0.39, 3690, 5.3, 0.25, 0, 0, 0, 0, 1, 4615, 12, 0.0)),
+    dict(offsets=[0, 10], eps=[0.1], field=[1], galaxy=(606, 0.39, 3690, 5.3, 0.25, 0, 0, 0, 0, 1, -1.0, 12, 100)),
 ])
 def test_invalid_systems_rejected_on_host(bad):
     s = nbody.System(**bad)
@@ -123,3 +127,18 @@ def test_workspace_bound_at_split_boundaries():
         for prec in ("fp32ds", "fp32dl", "fp64"):
             ws = nbody.nbody_workspace_bytes(None, nbody.System(offs, 1e-3, prec=prec))
             assert ws <= nbody.nbody_workspace_bytes_max(int(offs[-1]), len(sizes)), (sizes, prec)
+
+
+def test_second_galaxy_model_accepted_and_deferred_clusters_fit_the_bound():
+    """The Allen & Santillan model needs no vh or dh; its field clusters are finished by the combine
+    pass, so even unsplit ones take partial-sum rows, which the batch-independent bound covers."""
+    from paper_1003_3896_amd import inputs
+    offs = np.array([0, 1, 3, 203, 458, 714, 1714, 5714])
+    for fld in ([1] * 7, [1, 0, 1, 0, 1, 0, 1]):
+        s = nbody.System(offs, 1e-3, fld, 1.0, inputs.ALLEN_SANTILLAN)
+        ws = nbody.nbody_workspace_bytes(None, s)
+        s0 = nbody.System(offs, 1e-3, fld, 1.0, inputs.GALAXY)
+        assert ws > nbody.nbody_workspace_bytes(None, s0)   # the deferred clusters' partial rows
+        assert ws <= nbody.nbody_workspace_bytes_max(int(offs[-1]), len(offs) - 1)
+    big = nbody.System([0, 5_000_000], 1e-3, [1], 1.0, inputs.ALLEN_SANTILLAN)
+    assert nbody.nbody_workspace_bytes(None, big) <= nbody.nbody_workspace_bytes_max(5_000_000, 1)

@@ -54,3 +54,13 @@ def test_black_hole_set_up():
     assert abs(cm[0] - 10.0) < 1e-12 and abs(vcm[1] - 0.001 * inputs.V_CIRC_10) < 1e-15
     assert b.galaxy[:7] == inputs.GALAXY and b.galaxy[7] == 50.0 and b.galaxy[8] == b.eps[0]
     assert b.meta["integrator"] == "sym6" and b.meta["dt"] == 1e-4 and b.meta["steps"] == 40000
+
+
+def test_allen_santillan_parameters_match_the_fixture(oracle_mod):
+    """The generator's Allen & Santillan parameter tuple is the one the oracle's pins use, and its
+    solar-circle speed is the oracle's circular speed there."""
+    from test_oracle_field import _as91
+    g, gal = _as91()
+    assert tuple(inputs.ALLEN_SANTILLAN) == tuple(gal)
+    a, _ = oracle_mod.ext_field(np.array([[inputs.AS91_SUN_R, 0.0, 0.0]]), galaxy=inputs.ALLEN_SANTILLAN)
+    assert abs(np.sqrt(-a[0, 0] * inputs.AS91_SUN_R) - inputs.AS91_SUN_VC) < 0.05
