@@ -242,8 +242,9 @@ __device__ __forceinline__ void reduce_and_finish(const Args& a, const DevCluste
   if (sub != 0) return;
   if (c.split > 1 || (c.flags & kFlagDefer)) {
     // one j-range of a split cluster (or the only range of a deferred one): the combine pass adds
-    // the ranges in range order and finishes the particles (kernel boundaries, not device-scope fences, order the two: a fence
-    // inside this persistent kernel would write back and invalidate the XCD's L2)
+    // the ranges in range order and finishes the particles (kernel boundaries, not device-scope
+    // fences, order the two: a fence inside this persistent kernel would write back and invalidate
+    // the XCD's L2)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int li = ibase + k * 64;
