@@ -133,8 +133,10 @@ void nbody_destroy(nbody_ctx* ctx);
  * nbody_last_error() says why): 32 bytes per particle, plus 32 bytes per particle and j-range
  * for clusters whose sums are split into several source ranges (a cluster of N particles uses
  * about 2^22/N ranges, a power of two of at most 8 (16 from 2^15 particles on) with at least 128
- * sources each, so clusters of 256..2^21 particles are split), plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB
- * per cluster for the sort of NB_FP32DL, and for its per-item frames and far-tile bits 32 bytes per
+ * sources each, so clusters of 256..2^21 particles are split; an unsplit cluster in the
+ * NB_GALAXY_ALLEN_SANTILLAN field takes one such range too, since a separate pass finishes it),
+ * plus 48 bytes per particle, 4 KiB per 2048 particles and 4 KiB per cluster for the sort of
+ * NB_FP32DL, and for its per-item frames and far-tile bits 32 bytes per
  * 64 particles and range plus N_b^2 / 2^15 bytes per cluster, plus O(B + N/64) bookkeeping.  The
  * workspace must be 256-byte aligned;
  * its contents are the library's between calls (the caller must not modify it while calls using
