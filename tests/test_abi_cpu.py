@@ -142,3 +142,28 @@ def test_second_galaxy_model_accepted_and_deferred_clusters_fit_the_bound():
         assert ws <= nbody.nbody_workspace_bytes_max(int(offs[-1]), len(offs) - 1)
     big = nbody.System([0, 5_000_000], 1e-3, [1], 1.0, inputs.ALLEN_SANTILLAN)
     assert nbody.nbody_workspace_bytes(None, big) <= nbody.nbody_workspace_bytes_max(5_000_000, 1)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets that a C compiler gives
+    the header's structures (a layout drift would pass wrong values silently)."""
+    import subprocess
+    structs = {"nbody_galaxy": nbody.nbody_galaxy, "nbody_system": nbody.nbody_system, "nbody_tile": nbody.nbody_tile}
+    src = ['#include <stddef.h>', '#include <stdio.h>', '#include "nbody.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        src.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            src.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    src += ['  return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
